@@ -1,0 +1,247 @@
+#!/usr/bin/env python
+"""ChFSI benchmark on one MI355X.
+
+One step = one ChFSI pass over the whole block: the degree-m Chebyshev filter
+of every 128-vector block, Cholesky-Gram-Schmidt and Rayleigh-Ritz (with
+residual norms), all through the C ABI.  The default workload is the
+large periodic system: 20^3 cells, p = 6 (3.456 M spinor dofs), 200-Gaussian
+V_eff, noncollinear B_xc, 64 pseudo-atoms with l <= 2 spin-orbit projectors,
+N = 512 vectors filtered in 4 blocks of 128, Chebyshev degree 24, Gamma point.
+
+Printed JSON (one line, rank 0):
+  value        FP64 filter throughput, TFLOP/s, algorithmic count (a complex
+               multiply-add = 8 flops) over the filter sections of the timed passes
+  ms_per_step  wall time per FP64 pass (filter + CholGS + RR), the K timed passes
+  roofline     the FP64 cell-product kernel (dominant): algorithmic flops per
+               launch / mean launch time from HIP events, against 78.6 TFLOP/s
+  mixed        the same passes with FP32 cell/projector products (applies
+               1..m-1), from the same start: per-pass time, speedup and the
+               largest Ritz-value difference from the FP64 run
+  cpu_baseline the FP64 oracle on a bounded sample (see `sample`)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6     # TFLOP/s, MI355X dense FP64 (vector = matrix)
+PEAK_FP32 = 157.3    # TFLOP/s, MI355X dense FP32 matrix
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_operator(s, torch):
+    import synth
+    from paper_2410_02754_amd import Operator
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts)
+    t = time.perf_counter()
+    pts = op.quad_points().reshape(-1, 3)
+    V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+    B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+    log(f"[bench] fields at {pts.shape[0]} quadrature points: {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    op.set_local(V, B)
+    del V, B
+    log(f"[bench] cell operators: {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    op.set_atoms(s.atoms)
+    log(f"[bench] projectors ({len(s.atoms)} atoms): {time.perf_counter() - t:.1f} s")
+    return op
+
+
+def run_passes(op, s, X, W, Wf, b, theta, n_pass, prec, torch, label):
+    """n_pass passes; returns (theta, resid, per-pass seconds, filter seconds, filter stats)."""
+    times, ftimes = [], []
+    fstats = {"flops": 0.0, "cell_flops": 0.0, "cell_exec": 0.0, "cell_ms": 0.0, "cell_launches": 0}
+    cell_key = "cell_fp64" if prec == "fp64" else "cell_fp32"
+    r = None
+    for p in range(n_pass):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, a0 = float(theta[-1]), float(theta[0])
+        op.stats_reset()
+        for c0 in range(0, s.n_vec, s.block):
+            op.cheb_filter(X[:, c0:c0 + s.block], Wf, s.degree, a, b, a0, prec=prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = op.stats()
+        fstats["flops"] += sum(st[k]["flops"] for k in ("cell_fp64", "cell_fp32", "nonlocal"))
+        # the dominant kernel: every cell launch of this precision (apply m is FP64 in mixed mode)
+        fstats["cell_flops"] += st[cell_key]["flops"]
+        fstats["cell_exec"] += st[cell_key]["exec_flops"]
+        fstats["cell_ms"] += st[cell_key]["ms"]
+        fstats["cell_launches"] += st[cell_key]["launches"]
+        op.chol_gs(X)
+        theta, r = op.rayleigh_ritz(X, W)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append(t2 - t0)
+        ftimes.append(t1 - t0)
+        log(f"[bench] {label} pass {p + 1}/{n_pass}: {t2 - t0:.2f} s (filter {t1 - t0:.2f} s), "
+            f"theta[0]={theta[0]:.10f} max resid {np.max(r):.2e}")
+    return theta, r, times, ftimes, fstats
+
+
+def start(op, s, X, W, torch):
+    op.fill_random(X, s.seed, n_total_cols=s.n_vec)
+    op.chol_gs(X)
+    return op.rayleigh_ritz(X, W)
+
+
+def cpu_baseline(s_name):
+    """The oracle, as it is, on a bounded sample of the workload: one H_hat
+    application to 64 vectors on a 3 x 3 x 3-cell periodic piece of the same
+    mesh (same h and p), with one pseudo-atom of the same kind."""
+    import synth
+    from oracle import hamiltonian as ham
+    big = synth.config(s_name)
+    h = big.box[0] / big.n_cells[0]
+    a0 = big.atoms[0]
+    s = synth.make_system("sample", n_cells=(3, 3, 3), box=(3 * h, 3 * h, 3 * h), p=big.p,
+                          n_gauss=2, n_atoms=1, lmax=a0.lmax, sigma=a0.sigma,
+                          rcut_sigmas=a0.rcut / a0.sigma, n_vec=big.block, seed=5)
+    t = time.perf_counter()
+    _, H, _, _, _ = ham.build(s, synth.veff, synth.bxc)
+    t_build = time.perf_counter() - t
+    X = synth.start_block(s, s.n_dof)
+    reps = 0
+    t = time.perf_counter()
+    while True:          # repeat the apply for about 10 s of CPU work
+        Y = H @ X
+        reps += 1
+        if time.perf_counter() - t > 10.0 or reps >= 50:
+            break
+    t_apply = (time.perf_counter() - t) / reps
+    n2 = 2 * (s.p + 1) ** 3
+    flops = s.n_cell_total * 8.0 * n2 * n2 * s.n_vec
+    for Ps, D in H.projs:
+        nsup = int(np.count_nonzero(Ps.getnnz(axis=1))) // 2
+        npj = D.shape[0] // 2
+        flops += 2 * 8.0 * nsup * npj * 2 * s.n_vec + 8.0 * (2 * npj) ** 2 * s.n_vec
+    del Y
+    return {"value": flops / t_apply / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{reps} H_hat applies to {s.n_vec} vectors on a 3x3x3-cell periodic piece of the "
+                       f"{s_name} mesh (p={s.p}, h={h:.2f} bohr, {s.n_dof} dofs, 1 atom l<={a0.lmax}); "
+                       f"scipy CSR x dense is single-threaded; {t_apply:.2f} s per apply, "
+                       f"{t_build:.1f} s assembly (untimed)"),
+            "apply_s": t_apply}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=os.environ.get("CHFSI_BENCH_WORKLOAD", "scale"))
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    torch.cuda.set_device(0)
+    s = synth.config(args.workload)
+    log(f"[bench] workload {s.name}: {s.n_cells} cells p={s.p} 2M={s.n_dof} N={s.n_vec} "
+        f"block={s.block} m={s.degree} atoms={len(s.atoms)}")
+    t = time.perf_counter()
+    op = build_operator(s, torch)
+    op.stats_enable(True)
+    t_setup = time.perf_counter() - t
+    X = torch.empty((s.n_dof, s.n_vec), dtype=torch.complex128, device="cuda")
+    W = torch.empty_like(X)
+    Wf = torch.empty((s.n_dof, s.block), dtype=torch.complex128, device="cuda")
+    v0 = torch.empty((s.n_dof, 1), dtype=torch.complex128, device="cuda")
+    op.fill_random(v0, s.seed + 1)
+    t = time.perf_counter()
+    lo, b = op.lanczos_bounds(v0[:, 0], 40)
+    t_lanczos = time.perf_counter() - t
+    del v0
+    log(f"[bench] Lanczos bounds ({t_lanczos:.2f} s): [{lo:.6f}, {b:.6f}]")
+
+    # FP64 passes
+    theta, _ = start(op, s, X, W, torch)
+    theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "fp64", torch, "fp64 warmup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta64, r64, times, ftimes, fst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "fp64", torch,
+                                                  "fp64")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    filt_tflops = fst["flops"] / sum(ftimes) / 1e12
+    cell_per_launch = fst["cell_flops"] / max(1, fst["cell_launches"])
+    cell_ms = fst["cell_ms"] / max(1, fst["cell_launches"])
+    achieved = cell_per_launch / (cell_ms * 1e-3) / 1e12 if cell_ms > 0 else 0.0
+    exec_tf = fst["cell_exec"] / (fst["cell_ms"] * 1e-3) / 1e12 if fst["cell_ms"] > 0 else 0.0
+
+    out = {
+        "metric": "ChFSI filter TFLOP/s + s per ChFSI pass; FP32 vs FP64 filter at 1e-7 Ha eigs",
+        "value": round(filt_tflops, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * total / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}: periodic {s.n_cells[0]}x{s.n_cells[1]}x{s.n_cells[2]} cells, "
+                               f"p={s.p}, {s.n_dof} spinor dofs, {len(s.atoms)} SOC atoms, "
+                               f"N={s.n_vec} in blocks of {s.block}, degree {s.degree}, Gamma",
+                   "n_dof": s.n_dof, "n_vec": s.n_vec, "block": s.block, "degree": s.degree,
+                   "parallelism": "single GPU"},
+        "s_per_pass": round(total / args.steps, 3),
+        "filter_s_per_pass": round(sum(ftimes) / args.steps, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4), "traffic": None,
+                     "kernel": "cell_apply_kernel<double> (gather + Pauli-form cell products + scatter-add)",
+                     "flops_per_launch": cell_per_launch, "mean_launch_ms": round(cell_ms, 4),
+                     "executed_mfma_tflops": round(exec_tf, 3),
+                     "executed_frac": round(exec_tf / PEAK_FP64, 4)},
+        "setup_s": round(t_setup, 2), "lanczos_s": round(t_lanczos, 3),
+        "theta_min": float(theta64[0]), "theta_max": float(theta64[-1]), "max_resid": float(np.max(r64)),
+    }
+
+    if not args.no_mixed:
+        theta, _ = start(op, s, X, W, torch)
+        theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "mixed", torch,
+                                       "mixed warmup")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        thetam, rm, mt, mft, mst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "mixed", torch, "mixed")
+        torch.cuda.synchronize()
+        mtotal = time.perf_counter() - t0
+        dth = np.abs(thetam - theta64)
+        m_ach = (mst["cell_flops"] / max(1, mst["cell_launches"])) / \
+            ((mst["cell_ms"] / max(1, mst["cell_launches"])) * 1e-3) / 1e12 if mst["cell_ms"] > 0 else 0.0
+        out["mixed"] = {
+            "filter_tflops": round(mst["flops"] / sum(mft) / 1e12, 4),
+            "s_per_pass": round(mtotal / args.steps, 3),
+            "filter_s_per_pass": round(sum(mft) / args.steps, 3),
+            "speedup_pass": round(total / mtotal, 3),
+            "speedup_filter": round(sum(ftimes) / sum(mft), 3),
+            "max_dtheta_vs_fp64_Ha": float(dth.max()),
+            "within_1e-7_Ha": bool(dth.max() <= 1e-7),
+            "cell_fp32_achieved_tflops": round(m_ach, 3),
+            "cell_fp32_frac_of_157.3": round(m_ach / PEAK_FP32, 4),
+        }
+        log(f"[bench] mixed: max |dtheta| vs fp64 = {dth.max():.3e} Ha")
+    op.close()
+    del X, W, Wf
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle on a bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline(s.name)
+        out["cpu_baseline"].pop("apply_s", None)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

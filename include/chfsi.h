@@ -1,0 +1,224 @@
+/*
+ * chfsi.h -- C ABI of the MI355X ChFSI library.
+ *
+ * Chebyshev-filtered subspace iteration on two-component complex spinor
+ * blocks under the finite-element Kohn-Sham Hamiltonian with noncollinear
+ * exchange field and spin-orbit nonlocal projectors (arXiv 2410.02754,
+ * Sec. III.A-B and Sec. IV.B).  The library applies the symmetrically scaled
+ * operator
+ *
+ *     H_hat^k = M_D^{-1/2} H^k M_D^{-1/2}                       (Sec. III.B.2)
+ *
+ * where H^k = H^{k,loc} + H^{k,nloc} is the FE matrix of eqn:FEHloc and
+ * eqn:FEHnloc (projectors eqn:CMat, coefficients Delta_{2chi+a,2chi'+b} =
+ * D^{chi chi'}_{ab}) and M_D is the diagonal GLL (lumped) overlap.  H_hat^k has
+ * the spectrum of M_D^{-1} H^k; a block Y of H_hat^k corresponds to the FE
+ * coefficients U = M_D^{-1/2} Y.
+ *
+ * Conventions shared by every call
+ *  - Memory: pointers named *_d and all multivector arguments (X, Y, work,
+ *    v0) are DEVICE pointers owned by the caller; *_h pointers are host
+ *    memory owned by the caller.  The library never frees caller memory.  The
+ *    context owns everything it builds (cell matrices, projector tables,
+ *    internal scratch) and frees it in chfsi_destroy.
+ *  - Multivector layout: row-major [2M][ld] complex numbers, interleaved
+ *    (re, im).  Row r = 2 I + alpha is node I, spin alpha (eqn:GHEP); the n_vec
+ *    columns of a row are contiguous.  ld >= n_vec.  complex128 everywhere
+ *    (mixed precision converts internally).  A block of a wider array is
+ *    passed as (pointer to its first column, n_vec, ld of the wide array).
+ *  - Streams: all device work is enqueued on the HIP stream given to
+ *    chfsi_create.  Calls that return host data (ritz_h, resid_h, bad_col,
+ *    lo, hi) synchronise that stream before returning; the others are
+ *    asynchronous with respect to the host.
+ *  - Errors: every call returns CHFSI_OK (0) or a negative status; arguments
+ *    are validated before any launch.  chfsi_last_error(ctx) returns a text
+ *    description of the most recent failure.  No C++ exception crosses the
+ *    ABI.  A context is not thread-safe.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chfsi_ctx chfsi_ctx;
+
+enum chfsi_status {
+  CHFSI_OK = 0,
+  CHFSI_EINVAL = -1,      /* invalid argument (null pointer, size, range)        */
+  CHFSI_ENOMEM = -2,      /* device or host allocation failed                     */
+  CHFSI_EHIP = -3,        /* a HIP runtime call or kernel launch failed           */
+  CHFSI_ENOTPD = -4,      /* Gram matrix not positive definite (chol_gs)          */
+  CHFSI_ENONHERM = -5,    /* a Delta override is not Hermitian                    */
+  CHFSI_ENONFINITE = -6,  /* NaN/Inf in an input field or a reduced matrix        */
+  CHFSI_ESTATE = -7       /* call out of order (e.g. apply before set_local)      */
+};
+
+enum chfsi_quad { CHFSI_QUAD_GL = 0, CHFSI_QUAD_GLL = 1 };
+enum chfsi_prec { CHFSI_PREC_FP64 = 0, CHFSI_PREC_MIXED = 1 };
+
+/* Mesh of an orthorhombic periodic box (Sec. III.A).
+ *   n_cells[d] >= 2 hexahedral cells per direction, box[d] > 0 bohr,
+ *   p in 1..8: degree of the GLL Lagrange basis (n_p = p+1 nodes per direction),
+ *   quad: CHFSI_QUAD_GL = tensor Gauss-Legendre rule with n_q points per
+ *         direction for all cell integrals (eqn:cellIntegrals), 1 <= n_q <= 12;
+ *         CHFSI_QUAD_GLL = collocation at the GLL nodes (n_q ignored, = p+1),
+ *   n_k >= 1 k-points kpts[n_k][3] (host, Cartesian, 1/bohr); k enters through
+ *   the Bloch form of the operator (eqn:HnlocPeriodic and the k-terms of
+ *   eqn:FEHloc). */
+typedef struct {
+  int n_cells[3];
+  double box[3];
+  int p;
+  int quad;
+  int n_q;
+  int n_k;
+  const double* kpts;
+} chfsi_mesh_desc;
+
+/* One pseudo-atom with Gaussian real-harmonic projectors (stand-in for the
+ * ONCV projectors of eqn:nlOP):
+ *   p_lm(r) = c_l r^l Y_lm(r_hat) exp(-r^2/(2 sigma^2)) for r < rcut, else 0,
+ *   c_l^2 = 2/(Gamma(l+3/2) sigma^(2l+3)); real harmonics ordered
+ *   l=0; l=1 (x,y,z); l=2 (xy, yz, 3z^2-r^2, xz, x^2-y^2); l = 0..lmax <= 2.
+ *   Delta (index 2 chi + alpha) = D0_l within each shell + dso L.S, S = sigma/2.
+ *   delta_override: NULL, or host [2 n_pj][2 n_pj] complex128 (interleaved,
+ *   row-major) replacing Delta; must be Hermitian (else CHFSI_ENONHERM). */
+typedef struct {
+  double pos[3];
+  int lmax;
+  double sigma;
+  double rcut;
+  double d0[3];
+  double dso;
+  const double* delta_override;
+} chfsi_atom_desc;
+
+/* Build the mesh: numbering, cell colouring, reference-cell tables, lumped
+ * mass (Sec. III.A; Sec. III.B.2).  hip_stream: a hipStream_t (NULL = default
+ * stream).  On success *out owns the context. */
+int chfsi_create(const chfsi_mesh_desc* desc, void* hip_stream, chfsi_ctx** out);
+
+/* Free everything the context owns.  ctx may be NULL. */
+int chfsi_destroy(chfsi_ctx* ctx);
+
+/* Sizes: number of global nodes M, spinor dofs 2M, cells E, quadrature points
+ * per cell, cell colours of the scatter-add assembly.  Any pointer may be NULL. */
+int chfsi_sizes(const chfsi_ctx* ctx, int64_t* n_nodes, int64_t* n_dof, int* n_cells,
+                int* nq3, int* n_colours);
+
+/* Physical quadrature points, host [E][nq^3][3], cell e = cx + nx (cy + ny cz),
+ * point q = qx + nq (qy + nq qz).  The fields of chfsi_set_local are sampled
+ * at exactly these points. */
+int chfsi_quad_points(const chfsi_ctx* ctx, double* xyz_h);
+
+/* Local fields at the quadrature points (eqn:FEHloc, eqn:FEHlocEl): veff_d
+ * [E][nq^3] and bxc_d [E][nq^3][3] (device, float64).  Builds every cell
+ * operator for every k-point (FP64, plus the FP32 copy for mixed precision).
+ * CHFSI_ENONFINITE if a value is NaN/Inf. */
+int chfsi_set_local(chfsi_ctx* ctx, const double* veff_d, const double* bxc_d);
+
+/* Replace the set of pseudo-atoms (eqn:FEHnloc, eqn:CMat).  Builds the
+ * Bloch-phased, image-summed and M_D^{-1/2}-scaled projector tables for every
+ * k-point.  n_atoms may be 0. */
+int chfsi_set_atoms(chfsi_ctx* ctx, int n_atoms, const chfsi_atom_desc* atoms);
+
+/* Y = H_hat^k X for k-point ik (Sec. IV.B: extraction, cell products, nonlocal
+ * projector terms, assembly).  X_d, Y_d: [2M][ldx], [2M][ldy] complex128,
+ * distinct.  prec: CHFSI_PREC_FP64, or CHFSI_PREC_MIXED (cell products and
+ * projector products in FP32 with FP32 accumulation, converted on load/store). */
+int chfsi_apply_H(chfsi_ctx* ctx, int ik, const void* X_d, int64_t ldx, void* Y_d, int64_t ldy,
+                  int n_vec, int prec);
+
+/* Degree-m Chebyshev filter (eqn:chebfilt) damping [a, b] and amplifying the
+ * spectrum below a, in the scaled three-term form: e=(b-a)/2, c=(b+a)/2,
+ * sigma_1 = e/(a0-c), Y_1 = (sigma_1/e)(H - c)X, sigma_{k+1} = 1/(2/sigma_1 -
+ * sigma_k), Y_{k+1} = (2 sigma_{k+1}/e)(H - c)Y_k - sigma_k sigma_{k+1} Y_{k-1}.
+ * In place on X_d [2M][ldx]; work_d [2M][ldw] (ldw >= n_vec) is overwritten.
+ * Requires a0 < a < b and degree >= 1 (else CHFSI_EINVAL).  prec_mode
+ * CHFSI_PREC_MIXED runs applies 1..m-1 in FP32 and apply m in FP64; the
+ * recurrence itself is always FP64. */
+int chfsi_cheb_filter(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
+                      int n_vec, int degree, double a, double b, double a0, int prec_mode);
+
+/* Cholesky-Gram-Schmidt: S = X^H X (FP64), S = L L^H, X <- X L^{-H}, so that
+ * the columns become orthonormal with the same span (the orthonormalisation
+ * before the Rayleigh-Ritz step, Sec. III.B.2).  On CHFSI_ENOTPD *bad_col (if
+ * non-NULL) is the first column whose pivot is not positive and X is left
+ * unchanged. */
+int chfsi_chol_gs(chfsi_ctx* ctx, void* X_d, int64_t ldx, int n_vec, int* bad_col);
+
+/* Rayleigh-Ritz on an orthonormal block (Sec. III.B.2): W = H_hat^k X,
+ * H_p = X^H W, H_p = Q diag(theta) Q^H (ascending), X <- X Q.  ritz_h[n_vec]
+ * receives theta; if resid_h is non-NULL it receives ||H_hat x_i - theta_i x_i||.
+ * work_d [2M][ldw] (ldw >= n_vec) is overwritten.  FP64 throughout. */
+int chfsi_rayleigh_ritz(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
+                        int n_vec, double* ritz_h, double* resid_h);
+
+/* Spectral bounds by `steps` Lanczos steps on H_hat^k from v0_d [2M]
+ * (complex128, device, not modified): *lo = smallest Ritz value of the
+ * tridiagonal, *hi = largest Ritz value + ||f_steps|| (an upper bound of the
+ * spectrum, Sec. III.B.2). */
+int chfsi_lanczos_bounds(chfsi_ctx* ctx, int ik, int steps, const void* v0_d, double* lo,
+                         double* hi);
+
+/* Fill rows [row0, row0+n_rows) x columns [col0, col0+n_vec) of a seeded
+ * [..][n_total_cols] multivector into X_d [n_rows][ld]:
+ * X[r][n] = u(2j) + i u(2j+1), j = r * n_total_cols + n, u(i) = 2 w - 1 with w
+ * the top 53 bits of the i-th SplitMix64 output for `seed` (Steele et al. 2014). */
+int chfsi_fill_random(chfsi_ctx* ctx, void* X_d, int64_t n_rows, int n_vec, int64_t ld,
+                      uint64_t seed, int64_t row0, int col0, int64_t n_total_cols);
+
+/* Per-stage timing (HIP events recorded on the context's stream around each
+ * launch of a stage; off by default).  Stages: */
+enum chfsi_stage {
+  CHFSI_STAGE_CELL_FP64 = 0,  /* gather + FP64 cell products + scatter-add, one launch per colour */
+  CHFSI_STAGE_CELL_FP32 = 1,  /* the same in FP32 (mixed precision)                              */
+  CHFSI_STAGE_NONLOCAL = 2,   /* projector contraction, coupling and back-product                 */
+  CHFSI_STAGE_AXPY = 3,       /* recurrence initialisation / element-wise passes                  */
+  CHFSI_STAGE_GRAM = 4,       /* X^H Y overlap and projected-Hamiltonian products                 */
+  CHFSI_STAGE_ROTATE = 5,     /* in-place subspace rotations X <- X Q                             */
+  CHFSI_STAGE_HOST_DENSE = 6, /* host Cholesky / inverse / Hermitian eigensolver (wall time)      */
+  CHFSI_N_STAGES = 7
+};
+/* Accumulated totals of one stage since the last reset.  flops: algorithmic
+ * count (a complex multiply-add = 8 real flops; for the cell products
+ * 8 (2 n_p^3)^2 N per cell); exec_flops: MFMA flops actually issued (padded
+ * tiles, Pauli form); bytes: algorithmic HBM bytes (operator entries read
+ * once, vector rows gathered / read-added-written once). */
+typedef struct {
+  int64_t launches;
+  double ms;
+  double flops;
+  double exec_flops;
+  double bytes;
+} chfsi_stage_stats;
+
+/* Enable (1) or disable (0) stage timing. */
+int chfsi_stats_enable(chfsi_ctx* ctx, int enable);
+
+/* Synchronise the stream and write the totals of all CHFSI_N_STAGES stages
+ * into out[CHFSI_N_STAGES] (host). */
+int chfsi_stats_read(chfsi_ctx* ctx, chfsi_stage_stats* out);
+
+/* Zero the totals. */
+int chfsi_stats_reset(chfsi_ctx* ctx);
+
+/* Block until all work enqueued by the context has finished. */
+int chfsi_sync(chfsi_ctx* ctx);
+
+/* Text of the most recent error on ctx (or of the last failed create when ctx
+ * is NULL).  Valid until the next call on the same context. */
+const char* chfsi_last_error(const chfsi_ctx* ctx);
+
+/* Library version string. */
+const char* chfsi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHFSI_H */

@@ -1,0 +1,189 @@
+"""Thin wrapper of one chfsi context (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+_PREC = {"fp64": PREC_FP64, "mixed": PREC_MIXED, PREC_FP64: PREC_FP64, PREC_MIXED: PREC_MIXED}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _block(t, name):
+    """(pointer, ld, n_vec) of a row-major complex128 CUDA matrix or column block."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise ValueError(f"{name} must be contiguous")
+        return t.data_ptr(), 1, 1
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major block (unit column stride)")
+    return t.data_ptr(), t.stride(0), t.shape[1]
+
+
+class Operator:
+    """H_hat^k = M_D^{-1/2} H^k M_D^{-1/2} on one GPU, with the ChFSI steps.
+
+    All tensors must live on the current CUDA (HIP) device; every call is
+    enqueued on the torch stream that was current when the operator was built.
+    """
+
+    def __init__(self, n_cells: Sequence[int], box: Sequence[float], p: int, quad: str = "gl",
+                 n_q: Optional[int] = None, kpts=None, stream=None):
+        torch = _torch()
+        self.lib = _lib.load()
+        k = np.zeros((1, 3)) if kpts is None else np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 3)
+        self._kbuf = (C.c_double * k.size)(*k.ravel().tolist())
+        d = _lib.MeshDesc()
+        d.n_cells = (C.c_int * 3)(*[int(x) for x in n_cells])
+        d.box = (C.c_double * 3)(*[float(x) for x in box])
+        d.p = int(p)
+        d.quad = 1 if quad == "gll" else 0
+        d.n_q = int(n_q if n_q else p + 1)
+        d.n_k = int(k.shape[0])
+        d.kpts = C.cast(self._kbuf, C.POINTER(C.c_double))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        ctx = C.c_void_p()
+        rc = self.lib.chfsi_create(C.byref(d), C.c_void_p(stream), C.byref(ctx))
+        _lib.check(rc, None)
+        self.ctx = ctx
+        nn, nd = C.c_int64(), C.c_int64()
+        ne, nq3, ncol = C.c_int(), C.c_int(), C.c_int()
+        _lib.check(self.lib.chfsi_sizes(ctx, C.byref(nn), C.byref(nd), C.byref(ne), C.byref(nq3),
+                                        C.byref(ncol)), ctx)
+        self.n_nodes, self.n_dof = nn.value, nd.value
+        self.n_cells, self.nq3, self.n_colours = ne.value, nq3.value, ncol.value
+        self.n_k = int(k.shape[0])
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.chfsi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        _lib.check(rc, self.ctx)
+
+    # ---------------------------------------------------------------- setup
+    def quad_points(self) -> np.ndarray:
+        out = np.zeros((self.n_cells, self.nq3, 3))
+        self._chk(self.lib.chfsi_quad_points(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def set_local(self, V, B):
+        torch = _torch()
+        for t, shp in ((V, (self.n_cells, self.nq3)), (B, (self.n_cells, self.nq3, 3))):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+                raise ValueError(f"field must be a contiguous float64 CUDA tensor of shape {shp}")
+        self._chk(self.lib.chfsi_set_local(self.ctx, C.c_void_p(V.data_ptr()), C.c_void_p(B.data_ptr())))
+
+    def set_atoms(self, atoms: Iterable, delta_overrides=None):
+        atoms = list(atoms)
+        arr = (_lib.AtomDesc * max(1, len(atoms)))()
+        keep = []
+        for i, a in enumerate(atoms):
+            arr[i].pos = (C.c_double * 3)(*[float(x) for x in a.pos])
+            arr[i].lmax = int(a.lmax)
+            arr[i].sigma = float(a.sigma)
+            arr[i].rcut = float(a.rcut)
+            d0 = list(a.d0) + [0.0] * (3 - len(a.d0))
+            arr[i].d0 = (C.c_double * 3)(*d0[:3])
+            arr[i].dso = float(a.dso)
+            ov = None if delta_overrides is None else delta_overrides[i]
+            if ov is not None:
+                buf = np.ascontiguousarray(np.asarray(ov, dtype=np.complex128)).view(np.float64)
+                keep.append(buf)
+                arr[i].delta_override = buf.ctypes.data_as(C.POINTER(C.c_double))
+            else:
+                arr[i].delta_override = None
+        self._chk(self.lib.chfsi_set_atoms(self.ctx, len(atoms), arr))
+
+    # ---------------------------------------------------------------- hot path
+    def apply_H(self, X, Y, ik: int = 0, prec="fp64"):
+        px, ldx, n = _block(X, "X")
+        py, ldy, ny = _block(Y, "Y")
+        if ny != n or X.shape[0] != self.n_dof or Y.shape[0] != self.n_dof:
+            raise ValueError("X and Y must both be [2M][n_vec]")
+        self._chk(self.lib.chfsi_apply_H(self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(py), ldy, n,
+                                         _PREC[prec]))
+        return Y
+
+    def cheb_filter(self, X, work, degree: int, a: float, b: float, a0: float, ik: int = 0,
+                    prec="fp64"):
+        px, ldx, n = _block(X, "X")
+        pw, ldw, nw = _block(work, "work")
+        if nw < n or X.shape[0] != self.n_dof or work.shape[0] != self.n_dof:
+            raise ValueError("work must be [2M][>= n_vec]")
+        self._chk(self.lib.chfsi_cheb_filter(self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(pw), ldw,
+                                             n, int(degree), float(a), float(b), float(a0),
+                                             _PREC[prec]))
+        return X
+
+    def chol_gs(self, X):
+        px, ldx, n = _block(X, "X")
+        bad = C.c_int(-1)
+        rc = self.lib.chfsi_chol_gs(self.ctx, C.c_void_p(px), ldx, n, C.byref(bad))
+        if rc != 0:
+            err = _lib.ChfsiError(rc, self.lib.chfsi_last_error(self.ctx).decode())
+            err.bad_col = bad.value
+            raise err
+        return X
+
+    def rayleigh_ritz(self, X, work, ik: int = 0, resid: bool = True):
+        px, ldx, n = _block(X, "X")
+        pw, ldw, nw = _block(work, "work")
+        theta = np.zeros(n)
+        r = np.zeros(n) if resid else None
+        self._chk(self.lib.chfsi_rayleigh_ritz(
+            self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(pw), ldw, n,
+            theta.ctypes.data_as(C.POINTER(C.c_double)),
+            r.ctypes.data_as(C.POINTER(C.c_double)) if resid else None))
+        return theta, r
+
+    def lanczos_bounds(self, v0, steps: int = 40, ik: int = 0):
+        pv, _, _ = _block(v0, "v0")
+        lo, hi = C.c_double(), C.c_double()
+        self._chk(self.lib.chfsi_lanczos_bounds(self.ctx, ik, int(steps), C.c_void_p(pv),
+                                                C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def fill_random(self, X, seed: int, row0: int = 0, col0: int = 0, n_total_cols=None):
+        px, ld, n = _block(X, "X")
+        ntc = n if n_total_cols is None else int(n_total_cols)
+        self._chk(self.lib.chfsi_fill_random(self.ctx, C.c_void_p(px), X.shape[0], n, ld,
+                                             C.c_uint64(seed), row0, col0, ntc))
+        return X
+
+    def stats_enable(self, on: bool = True):
+        self._chk(self.lib.chfsi_stats_enable(self.ctx, 1 if on else 0))
+
+    def stats_reset(self):
+        self._chk(self.lib.chfsi_stats_reset(self.ctx))
+
+    def stats(self) -> dict:
+        """Per-stage totals since the last reset: launches, ms, flops, exec_flops, bytes."""
+        arr = (_lib.StageStats * len(_lib.STAGES))()
+        self._chk(self.lib.chfsi_stats_read(self.ctx, arr))
+        return {name: {f: getattr(arr[i], f) for f, _ in _lib.StageStats._fields_}
+                for i, name in enumerate(_lib.STAGES)}
+
+    def sync(self):
+        self._chk(self.lib.chfsi_sync(self.ctx))

@@ -1,0 +1,374 @@
+// extern "C" entry points of the ChFSI library: argument validation, context
+// lifetime, and the host-side sequencing of the device steps.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <chrono>
+#include <new>
+
+#include "internal.h"
+
+using namespace chfsi;
+
+namespace chfsi {
+void tridiag_eigvals(std::vector<double> d, std::vector<double> e, std::vector<double>& w);
+}
+
+static std::string g_create_error;
+
+#define API_BEGIN(ctx) \
+  try {
+#define API_END(ctx)                                           \
+  }                                                            \
+  catch (const chfsi::Error& e) {                              \
+    if (ctx) (ctx)->last_error = e.msg;                        \
+    return e.code;                                             \
+  }                                                            \
+  catch (const std::bad_alloc&) {                              \
+    if (ctx) (ctx)->last_error = "host allocation failed";     \
+    return CHFSI_ENOMEM;                                       \
+  }                                                            \
+  catch (const std::exception& e) {                            \
+    if (ctx) (ctx)->last_error = e.what();                     \
+    return CHFSI_EINVAL;                                       \
+  }                                                            \
+  return CHFSI_OK;
+
+static KPoint& kpoint(chfsi_ctx* c, int ik) {
+  CHFSI_CHECK(ik >= 0 && ik < (int)c->kp.size(), CHFSI_EINVAL, "k-point index out of range");
+  return *c->kp[ik];
+}
+
+static void check_block(const chfsi_ctx* c, const void* p, int64_t ld, int n_vec, const char* what) {
+  CHFSI_CHECK(p != nullptr, CHFSI_EINVAL, std::string(what) + " is NULL");
+  CHFSI_CHECK(n_vec >= 1, CHFSI_EINVAL, "n_vec must be >= 1");
+  CHFSI_CHECK(ld >= n_vec, CHFSI_EINVAL, std::string("ld of ") + what + " must be >= n_vec");
+  CHFSI_CHECK(((uintptr_t)p % 16) == 0, CHFSI_EINVAL, std::string(what) + " must be 16-byte aligned");
+  (void)c;
+}
+
+static void require_operator(const chfsi_ctx* c) {
+  CHFSI_CHECK(c->have_local, CHFSI_ESTATE, "chfsi_set_local has not been called");
+}
+
+extern "C" {
+
+const char* chfsi_version(void) { return "chfsi-mi355x 0.1"; }
+
+const char* chfsi_last_error(const chfsi_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
+}
+
+int chfsi_create(const chfsi_mesh_desc* d, void* stream, chfsi_ctx** out) {
+  chfsi_ctx* c = nullptr;
+  try {
+    CHFSI_CHECK(d != nullptr && out != nullptr, CHFSI_EINVAL, "desc and out must be non-NULL");
+    for (int k = 0; k < 3; ++k) {
+      CHFSI_CHECK(d->n_cells[k] >= 2 && d->n_cells[k] <= 4096, CHFSI_EINVAL, "n_cells must be in [2, 4096]");
+      CHFSI_CHECK(d->box[k] > 0.0 && std::isfinite(d->box[k]), CHFSI_EINVAL, "box lengths must be > 0");
+    }
+    CHFSI_CHECK(d->p >= 1 && d->p <= kMaxP, CHFSI_EINVAL, "p must be in [1, 8]");
+    CHFSI_CHECK(d->quad == CHFSI_QUAD_GL || d->quad == CHFSI_QUAD_GLL, CHFSI_EINVAL, "unknown quadrature");
+    if (d->quad == CHFSI_QUAD_GL)
+      CHFSI_CHECK(d->n_q >= 1 && d->n_q <= kMaxNq, CHFSI_EINVAL, "n_q must be in [1, 12]");
+    CHFSI_CHECK(d->n_k >= 1 && d->kpts != nullptr, CHFSI_EINVAL, "need n_k >= 1 k-points");
+    const int64_t nodes = (int64_t)d->n_cells[0] * d->p * d->n_cells[1] * d->p * d->n_cells[2] * d->p;
+    CHFSI_CHECK(nodes < ((int64_t)1 << 30), CHFSI_EINVAL, "mesh too large for 32-bit node ids");
+    c = new chfsi_ctx();
+    for (int k = 0; k < 3; ++k) {
+      c->nc[k] = d->n_cells[k];
+      c->box[k] = d->box[k];
+    }
+    c->p = d->p;
+    c->np1 = d->p + 1;
+    c->quad = d->quad;
+    c->stream = (hipStream_t)stream;
+    c->ref = make_ref(d->p, d->quad, d->n_q);
+    c->nq = c->ref.nq;
+    build_mesh(c);
+    build_uniform_mats(c);
+    for (int ik = 0; ik < d->n_k; ++ik) {
+      KPoint* kp = new KPoint();
+      for (int k = 0; k < 3; ++k) kp->k[k] = d->kpts[3 * ik + k];
+      kp->gamma = kp->k[0] == 0.0 && kp->k[1] == 0.0 && kp->k[2] == 0.0;
+      kp->nmat = kp->gamma ? 4 : 5;
+      c->kp.push_back(kp);
+    }
+    CHFSI_HIP(hipStreamSynchronize(c->stream));
+    *out = c;
+    return CHFSI_OK;
+  } catch (const chfsi::Error& e) {
+    g_create_error = e.msg;
+    if (c) chfsi_destroy(c);
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    if (c) chfsi_destroy(c);
+    return CHFSI_ENOMEM;
+  }
+}
+
+int chfsi_destroy(chfsi_ctx* c) {
+  if (!c) return CHFSI_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto* k : c->kp) delete k;
+  delete c;
+  return CHFSI_OK;
+}
+
+int chfsi_sizes(const chfsi_ctx* c, int64_t* n_nodes, int64_t* n_dof, int* n_cells, int* nq3, int* n_colours) {
+  if (!c) return CHFSI_EINVAL;
+  if (n_nodes) *n_nodes = c->n_nodes;
+  if (n_dof) *n_dof = 2 * c->n_nodes;
+  if (n_cells) *n_cells = c->n_cells;
+  if (nq3) *nq3 = c->nq3;
+  if (n_colours) *n_colours = c->n_colours;
+  return CHFSI_OK;
+}
+
+int chfsi_quad_points(const chfsi_ctx* c, double* xyz) {
+  if (!c || !xyz) return CHFSI_EINVAL;
+  const int nq = c->nq;
+  for (int e = 0; e < c->n_cells; ++e) {
+    const int cc[3] = {e % c->nc[0], (e / c->nc[0]) % c->nc[1], e / (c->nc[0] * c->nc[1])};
+    for (int q = 0; q < c->nq3; ++q) {
+      const int qa[3] = {q % nq, (q / nq) % nq, q / (nq * nq)};
+      for (int d = 0; d < 3; ++d)
+        xyz[((size_t)e * c->nq3 + q) * 3 + d] = cc[d] * c->h[d] + (c->ref.xq[qa[d]] + 1.0) * 0.5 * c->h[d];
+    }
+  }
+  return CHFSI_OK;
+}
+
+int chfsi_set_local(chfsi_ctx* c, const double* V, const double* B) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  CHFSI_CHECK(V && B, CHFSI_EINVAL, "veff_d and bxc_d must be non-NULL");
+  CHFSI_CHECK(check_finite(c, V, (int64_t)c->n_cells * c->nq3), CHFSI_ENONFINITE, "veff has NaN/Inf");
+  CHFSI_CHECK(check_finite(c, B, (int64_t)c->n_cells * c->nq3 * 3), CHFSI_ENONFINITE, "bxc has NaN/Inf");
+  const int N = c->nloc;
+  for (auto* kp : c->kp) {
+    // uniform parts of the cell operator for this k:
+    //   U0 = kinetic + |k|^2/2 mass;  S = -(C - C^T)/2 with C = sum_d k_d C_d
+    // (the k-gradient term -i C of eqn:FEHloc, skew-symmetrised per cell; the
+    // symmetric part of C sums to zero over the periodic mesh)
+    const double k2 = kp->k[0] * kp->k[0] + kp->k[1] * kp->k[1] + kp->k[2] * kp->k[2];
+    std::vector<double> U0((size_t)N * N), S((size_t)N * N, 0.0);
+    for (size_t t = 0; t < U0.size(); ++t) U0[t] = c->Kin[t] + 0.5 * k2 * c->Mcons[t];
+    if (!kp->gamma)
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+          double cij = 0.0, cji = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            cij += kp->k[d] * c->Cgrad[d][(size_t)i * N + j];
+            cji += kp->k[d] * c->Cgrad[d][(size_t)j * N + i];
+          }
+          S[(size_t)i * N + j] = -0.5 * (cij - cji);
+        }
+    DevBuf<double> dU, dS;
+    dU.upload(U0.data(), U0.size(), c->stream);
+    dS.upload(S.data(), S.size(), c->stream);
+    launch_cell_setup(c, *kp, V, B, dU.ptr, dS.ptr);
+    launch_cell_to_f32(c, *kp);
+    CHFSI_HIP(hipStreamSynchronize(c->stream));
+  }
+  c->have_local = true;
+  API_END(c)
+}
+
+int chfsi_set_atoms(chfsi_ctx* c, int n_atoms, const chfsi_atom_desc* atoms) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  CHFSI_CHECK(n_atoms >= 0 && (n_atoms == 0 || atoms != nullptr), CHFSI_EINVAL, "bad atom list");
+  for (int a = 0; a < n_atoms; ++a) {
+    const auto& at = atoms[a];
+    CHFSI_CHECK(at.lmax >= 0 && at.lmax <= 2, CHFSI_EINVAL, "lmax must be in [0, 2]");
+    CHFSI_CHECK(at.sigma > 0.0 && at.rcut > 0.0, CHFSI_EINVAL, "sigma and rcut must be > 0");
+    for (int d = 0; d < 3; ++d) CHFSI_CHECK(std::isfinite(at.pos[d]), CHFSI_ENONFINITE, "atom position NaN/Inf");
+    if (at.delta_override) {
+      const int nd = 2 * (at.lmax + 1) * (at.lmax + 1);
+      for (int i = 0; i < nd; ++i)
+        for (int j = 0; j < nd; ++j) {
+          const double* a1 = at.delta_override + 2 * ((size_t)i * nd + j);
+          const double* a2 = at.delta_override + 2 * ((size_t)j * nd + i);
+          CHFSI_CHECK(std::isfinite(a1[0]) && std::isfinite(a1[1]), CHFSI_ENONFINITE, "Delta has NaN/Inf");
+          CHFSI_CHECK(std::fabs(a1[0] - a2[0]) <= 1e-12 * (1 + std::fabs(a1[0])) &&
+                          std::fabs(a1[1] + a2[1]) <= 1e-12 * (1 + std::fabs(a1[1])),
+                      CHFSI_ENONHERM, "Delta override is not Hermitian");
+        }
+    }
+  }
+  for (auto* kp : c->kp) build_nonlocal(c, *kp, n_atoms, atoms);
+  API_END(c)
+}
+
+int chfsi_apply_H(chfsi_ctx* c, int ik, const void* X, int64_t ldx, void* Y, int64_t ldy, int n_vec, int prec) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, Y, ldy, n_vec, "Y");
+  CHFSI_CHECK(X != Y, CHFSI_EINVAL, "X and Y must be distinct");
+  CHFSI_CHECK(prec == CHFSI_PREC_FP64 || prec == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
+  KPoint& kp = kpoint(c, ik);
+  apply_H(c, kp, (const double2*)X, ldx, (double2*)Y, ldy, n_vec, prec, 1.0, 0.0, 0.0);
+  API_END(c)
+}
+
+int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
+                      int degree, double a, double b, double a0, int prec_mode) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, work, ldw, n_vec, "work");
+  CHFSI_CHECK(X != work, CHFSI_EINVAL, "X and work must be distinct");
+  CHFSI_CHECK(degree >= 1, CHFSI_EINVAL, "degree must be >= 1");
+  CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
+              "filter bounds must satisfy a0 < a < b");
+  CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
+  KPoint& kp = kpoint(c, ik);
+  const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
+  const double sigma1 = e / (a0 - cc);
+  double sigma = sigma1;
+  double2* bufs[2] = {(double2*)X, (double2*)work};
+  const int64_t lds[2] = {ldx, ldw};
+  // Y_1 = (sigma_1/e)(H - c) X -> work
+  {
+    const double al = sigma1 / e;
+    const int prec = (prec_mode == CHFSI_PREC_MIXED && degree > 1) ? CHFSI_PREC_MIXED : CHFSI_PREC_FP64;
+    apply_H(c, kp, bufs[0], lds[0], bufs[1], lds[1], n_vec, prec, al, 0.0, -cc * al);
+  }
+  int cur = 1;   // buffer holding Y_k
+  for (int k = 2; k <= degree; ++k) {
+    const double sn = 1.0 / (2.0 / sigma1 - sigma);
+    const double al = 2.0 * sn / e;
+    const double be = -sigma * sn;
+    const int prec = (prec_mode == CHFSI_PREC_MIXED && k < degree) ? CHFSI_PREC_MIXED : CHFSI_PREC_FP64;
+    // Y_{k} = al (H - c) Y_{k-1} + be Y_{k-2}, written over Y_{k-2}
+    apply_H(c, kp, bufs[cur], lds[cur], bufs[cur ^ 1], lds[cur ^ 1], n_vec, prec, al, be, -cc * al);
+    cur ^= 1;
+    sigma = sn;
+  }
+  if (cur == 1) launch_copy_rows(c, bufs[0], ldx, bufs[1], ldw, 2 * c->n_nodes, n_vec);
+  API_END(c)
+}
+
+int chfsi_chol_gs(chfsi_ctx* c, void* X, int64_t ldx, int n_vec, int* bad_col) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  check_block(c, X, ldx, n_vec, "X");
+  if (bad_col) *bad_col = -1;
+  const int64_t rows = 2 * c->n_nodes;
+  std::vector<cplx> S;
+  gram(c, (const double2*)X, ldx, (const double2*)X, ldx, rows, n_vec, S, true);
+  for (const auto& v : S)
+    CHFSI_CHECK(std::isfinite(v.real()) && std::isfinite(v.imag()), CHFSI_ENONFINITE, "Gram matrix has NaN/Inf");
+  auto t0 = std::chrono::steady_clock::now();
+  const int bad = cholesky_lower(S, n_vec);
+  if (bad >= 0) {
+    if (bad_col) *bad_col = bad;
+    throw Error{CHFSI_ENOTPD, "Gram matrix not positive definite at column " + std::to_string(bad)};
+  }
+  std::vector<cplx> Linv, R((size_t)n_vec * n_vec);
+  lower_inverse(S, n_vec, Linv);
+  for (int i = 0; i < n_vec; ++i)
+    for (int j = 0; j < n_vec; ++j) R[(size_t)i * n_vec + j] = std::conj(Linv[(size_t)j * n_vec + i]);
+  stats_add_host(c, CHFSI_STAGE_HOST_DENSE,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+  rotate_inplace(c, (double2*)X, ldx, rows, n_vec, R, true);
+  API_END(c)
+}
+
+int chfsi_rayleigh_ritz(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
+                        double* ritz, double* resid) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, work, ldw, n_vec, "work");
+  CHFSI_CHECK(ritz != nullptr, CHFSI_EINVAL, "ritz_h must be non-NULL");
+  CHFSI_CHECK(X != work, CHFSI_EINVAL, "X and work must be distinct");
+  KPoint& kp = kpoint(c, ik);
+  const int64_t rows = 2 * c->n_nodes;
+  apply_H(c, kp, (const double2*)X, ldx, (double2*)work, ldw, n_vec, CHFSI_PREC_FP64, 1.0, 0.0, 0.0);
+  std::vector<cplx> Hp;
+  gram(c, (const double2*)X, ldx, (const double2*)work, ldw, rows, n_vec, Hp, true);
+  for (const auto& v : Hp)
+    CHFSI_CHECK(std::isfinite(v.real()) && std::isfinite(v.imag()), CHFSI_ENONFINITE, "projected H has NaN/Inf");
+  std::vector<double> w;
+  std::vector<cplx> Q;
+  auto t0 = std::chrono::steady_clock::now();
+  hermitian_eig(Hp, n_vec, w, Q);
+  stats_add_host(c, CHFSI_STAGE_HOST_DENSE,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+  rotate_inplace(c, (double2*)X, ldx, rows, n_vec, Q, false);
+  for (int i = 0; i < n_vec; ++i) ritz[i] = w[i];
+  if (resid) {
+    rotate_inplace(c, (double2*)work, ldw, rows, n_vec, Q, false);
+    column_resid_norms(c, (const double2*)work, ldw, (const double2*)X, ldx, rows, n_vec, w.data(), resid);
+  }
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  API_END(c)
+}
+
+int chfsi_lanczos_bounds(chfsi_ctx* c, int ik, int steps, const void* v0, double* lo, double* hi) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  CHFSI_CHECK(v0 && lo && hi, CHFSI_EINVAL, "v0_d, lo and hi must be non-NULL");
+  CHFSI_CHECK(steps >= 1 && steps <= 10000, CHFSI_EINVAL, "steps must be in [1, 10000]");
+  KPoint& kp = kpoint(c, ik);
+  const int64_t rows = 2 * c->n_nodes;
+  DevBuf<double2> vb;
+  vb.alloc((size_t)3 * rows);
+  double2* v = vb.ptr;
+  double2* w = v + rows;
+  double2* vp = w + rows;
+  const double n0 = std::sqrt(dot_re(c, (const double2*)v0, (const double2*)v0, rows));
+  CHFSI_CHECK(n0 > 0.0 && std::isfinite(n0), CHFSI_EINVAL, "v0 must be finite and nonzero");
+  launch_axpby_rows(c, v, 1, (const double2*)v0, 1, rows, 1, 0.0, 1.0 / n0);
+  launch_axpby_rows(c, vp, 1, v, 1, rows, 1, 0.0, 0.0);
+  double beta = 0.0;
+  std::vector<double> al, be;
+  for (int j = 0; j < steps; ++j) {
+    apply_H(c, kp, v, 1, w, 1, 1, CHFSI_PREC_FP64, 1.0, 0.0, 0.0);
+    const double alpha = dot_re(c, v, w, rows);
+    launch_axpby_rows(c, w, 1, v, 1, rows, 1, 1.0, -alpha);
+    launch_axpby_rows(c, w, 1, vp, 1, rows, 1, 1.0, -beta);
+    const double bn = std::sqrt(dot_re(c, w, w, rows));
+    al.push_back(alpha);
+    if (j < steps - 1) be.push_back(bn);
+    std::swap(vp, v);                                   // vp <- v
+    if (bn > 0.0) launch_axpby_rows(c, v, 1, w, 1, rows, 1, 0.0, 1.0 / bn);
+    beta = bn;
+    if (!(bn > 0.0)) break;
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  std::vector<double> th;
+  tridiag_eigvals(al, be, th);
+  *lo = th.front();
+  *hi = th.back() + beta;
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  API_END(c)
+}
+
+int chfsi_fill_random(chfsi_ctx* c, void* X, int64_t n_rows, int n_vec, int64_t ld, uint64_t seed, int64_t row0,
+                      int col0, int64_t ntc) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  check_block(c, X, ld, n_vec, "X");
+  CHFSI_CHECK(n_rows >= 0 && row0 >= 0 && col0 >= 0 && ntc >= col0 + n_vec, CHFSI_EINVAL, "bad fill extents");
+  launch_fill_random(c, (double2*)X, n_rows, n_vec, ld, seed, row0, col0, ntc);
+  API_END(c)
+}
+
+int chfsi_sync(chfsi_ctx* c) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  API_END(c)
+}
+
+}  // extern "C"

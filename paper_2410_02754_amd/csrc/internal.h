@@ -1,0 +1,221 @@
+// Private declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chfsi.h"
+
+namespace chfsi {
+
+using cplx = std::complex<double>;
+
+constexpr int kMaxP = 8;
+constexpr int kMaxNq = 12;
+constexpr int kRowBlk = 16;  // MFMA row granularity of the cell operator tiles
+constexpr int kKStep = 4;    // MFMA reduction depth per fragment
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define CHFSI_HIP(call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::chfsi::Error{CHFSI_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define CHFSI_CHECK(cond, code, msg)                                                  \
+  do {                                                                                \
+    if (!(cond)) throw ::chfsi::Error{(code), (msg)};                                 \
+  } while (0)
+
+// ---------------------------------------------------------------- device buffer
+template <class T>
+struct DevBuf {
+  T* ptr = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count <= n && ptr) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      throw Error{CHFSI_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void upload(const T* h, size_t count, hipStream_t s) {
+    alloc(count);
+    CHFSI_HIP(hipMemcpyAsync(ptr, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// ---------------------------------------------------------------- reference element (host)
+struct RefElement {
+  int p = 0, np1 = 0, nq = 0;
+  std::vector<double> xi, wgll;   // GLL nodes/weights
+  std::vector<double> xq, wq;     // quadrature points/weights (GL or GLL)
+  std::vector<double> B, D;       // [np1][nq] l_a(x_q), l_a'(x_q)
+};
+void gll_rule(int p, std::vector<double>& x, std::vector<double>& w);
+void gl_rule(int n, std::vector<double>& x, std::vector<double>& w);
+void lagrange_on(const std::vector<double>& nodes, const std::vector<double>& pts,
+                 std::vector<double>& B, std::vector<double>& D);
+RefElement make_ref(int p, int quad, int nq);
+
+// ---------------------------------------------------------------- nonlocal tables per k
+struct AtomTables {
+  int n_pj = 0;                 // orbitals (spinor columns = 2 n_pj)
+  int n_sup = 0;                // support nodes
+  int64_t node_off = 0;         // offset into the concatenated support arrays
+  std::vector<cplx> delta;      // [2 n_pj][2 n_pj]
+};
+
+struct NonlocalK {
+  int n_atoms = 0;
+  int max_pj = 0;
+  int64_t n_entries = 0;        // sum over atoms of n_sup
+  std::vector<AtomTables> atoms;
+  // device, concatenated over atoms (atom a occupies [node_off, node_off + n_sup))
+  DevBuf<int32_t> sup_node;     // [n_entries] global node
+  DevBuf<double2> proj;         // [n_entries][max_pj] M^{-1/2}-scaled P_hat (complex)
+  DevBuf<float2> proj32;        // same, FP32
+  DevBuf<double2> delta;        // [n_atoms][2 max_pj][2 max_pj]
+  DevBuf<int32_t> atom_off;     // [n_atoms + 1] entry offsets
+  DevBuf<int32_t> atom_npj;     // [n_atoms]
+  // chunked reduction work list for C = P^H X: chunks of kNlChunk entries
+  int n_chunks = 0;
+  DevBuf<int32_t> chunk_atom;   // [n_chunks]
+  DevBuf<int32_t> chunk_begin;  // [n_chunks]
+  DevBuf<int32_t> chunk_end;    // [n_chunks]
+  DevBuf<int32_t> atom_chunk0;  // [n_atoms + 1]
+  // node-centric back-product: unique nodes, each with its (entry, atom) list
+  int64_t n_unodes = 0;
+  DevBuf<int32_t> unode;        // [n_unodes] global node
+  DevBuf<int32_t> unode_off;    // [n_unodes + 1] into ulist
+  DevBuf<int32_t> ulist_entry;  // [n_entries] entry index
+  DevBuf<int32_t> ulist_atom;   // [n_entries]
+};
+constexpr int kNlChunk = 256;
+
+// ---------------------------------------------------------------- context
+struct KPoint {
+  double k[3];
+  bool gamma;
+  int nmat;                     // 4 at Gamma (Hp, Hm, Bx, By), 5 with the k-term S
+  DevBuf<double> cell64;        // tiled cell operators, FP64
+  DevBuf<float> cell32;         // FP32 copy
+  NonlocalK nl;
+};
+
+struct StageRec {
+  int stage;
+  hipEvent_t start, stop;
+  double flops, exec_flops, bytes;
+};
+
+}  // namespace chfsi
+
+struct chfsi_ctx {
+  int nc[3];
+  double box[3];
+  double h[3];
+  double J;
+  int p, np1, nloc, quad, nq, nq3;
+  int Nd[3];
+  int64_t n_nodes;
+  int n_cells;
+  hipStream_t stream;
+  chfsi::RefElement ref;
+  // numbering and colouring
+  std::vector<int32_t> cell_nodes_h;          // [E][nloc]
+  chfsi::DevBuf<int32_t> cell_nodes;          // [E][nloc]
+  int n_colours;
+  std::vector<int> colour_off;                // [n_colours + 1]
+  chfsi::DevBuf<int32_t> colour_cells;        // cells sorted by colour
+  std::vector<double> minv_sqrt_h;            // [M] M_D^{-1/2}
+  chfsi::DevBuf<double> minv_sqrt;
+  // cell operator tiling
+  int nrb;                                    // row blocks of 16 (padded)
+  int nkb;                                    // k-steps of 4 (padded to nrb*4)
+  // uniform reference matrices (host, real [nloc][nloc])
+  std::vector<double> Kin, Mcons;
+  std::vector<double> Cgrad[3];               // d-th component of the k-gradient matrix
+  std::vector<chfsi::KPoint*> kp;
+  bool have_local = false;
+  // internal scratch
+  chfsi::DevBuf<double> scratch;              // reductions, small matrices
+  chfsi::DevBuf<double> panel;                // row panel for in-place rotations
+  // stage timing
+  bool stats_on = false;
+  std::vector<chfsi::StageRec> pending;
+  std::vector<hipEvent_t> event_pool;
+  chfsi_stage_stats stats[CHFSI_N_STAGES] = {};
+  std::string last_error;
+};
+
+namespace chfsi {
+// Records HIP events around a stage's launches when timing is enabled.
+class StageTimer {
+ public:
+  StageTimer(chfsi_ctx* c, int stage, double flops, double exec_flops, double bytes);
+  ~StageTimer();
+ private:
+  chfsi_ctx* c_;
+  StageRec rec_;
+  bool on_;
+};
+void stats_resolve(chfsi_ctx* c);
+void stats_add_host(chfsi_ctx* c, int stage, double ms);
+
+// host setup (fe_host.cpp)
+void build_mesh(chfsi_ctx* c);
+void build_uniform_mats(chfsi_ctx* c);
+void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc* atoms);
+void angular_momentum_real(int l, std::vector<cplx>& L);   // [3][2l+1][2l+1]
+
+// dense host linear algebra (dense_host.cpp)
+int cholesky_lower(std::vector<cplx>& S, int n);           // returns -1 ok, else bad column
+void lower_inverse(const std::vector<cplx>& L, int n, std::vector<cplx>& Linv);
+void hermitian_eig(const std::vector<cplx>& A, int n, std::vector<double>& w, std::vector<cplx>& V);
+
+// device launchers (kernels.hip)
+void launch_cell_setup(chfsi_ctx* c, KPoint& kp, const double* V, const double* B,
+                       const double* U0, const double* S);
+void launch_cell_to_f32(chfsi_ctx* c, KPoint& kp);
+int check_finite(chfsi_ctx* c, const double* p, int64_t n);
+// W <- alpha H_hat X + beta W + gamma X   (W is not read when beta == 0)
+void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+             int n_vec, int prec, double alpha, double beta, double gamma);
+void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,
+                       int64_t rows, int n_vec, double beta, double gamma);
+void launch_copy_rows(chfsi_ctx* c, double2* dst, int64_t ldd, const double2* src, int64_t lds,
+                      int64_t rows, int n_vec);
+void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t ldy, int64_t rows,
+          int n, std::vector<cplx>& S, bool lower_only);
+void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n,
+                    const std::vector<cplx>& Q, bool upper_triangular);
+void column_resid_norms(chfsi_ctx* c, const double2* W, int64_t ldw, const double2* X, int64_t ldx,
+                        int64_t rows, int n, const double* theta, double* out);
+double dot_re(chfsi_ctx* c, const double2* x, const double2* y, int64_t rows);
+void launch_fill_random(chfsi_ctx* c, double2* X, int64_t n_rows, int n_vec, int64_t ld,
+                        uint64_t seed, int64_t row0, int col0, int64_t n_total_cols);
+}  // namespace chfsi

@@ -1,0 +1,904 @@
+// Device kernels and their launchers for gfx950 (CDNA4, wave64).
+//
+// Operator action (Sec. IV.B, "FE discretized matrix multivector product"):
+// extraction X_e = R_e X, cell products H_e X_e, nonlocal projector terms,
+// assembly Y = sum_e R_e^T Y_e.  The four steps run as
+//   1. an element-wise pass that initialises the output with the recurrence
+//      terms (beta W + gamma X),
+//   2. the projector contraction C_a = P_a^H X, the coupling C'_a = Delta_a C_a
+//      and the node-centric back-product W += P_a C'_a (eqn:FEHnloc),
+//   3. one launch per cell colour of the fused gather / MFMA cell product /
+//      scatter-add kernel; cells of one colour share no node, so the
+//      read-add-write of the epilogue needs no atomics and the result is
+//      bitwise reproducible.
+//
+// Cell operator storage ("Pauli form"): the spinor cell matrix of
+// eqn:FEHlocEl with the k-terms of eqn:FEHloc is, with every term scaled by
+// M_D^{-1/2} on both sides,
+//   [[A + Bz + iS, Bx - iBy], [Bx + iBy, A - Bz + iS]]
+// with A = kinetic + |k|^2/2 mass + V-weighted mass and B_d the B_d-weighted
+// masses (real symmetric) and S the skew-symmetrised k-gradient term (real
+// antisymmetric, zero at Gamma).  Each cell stores the real matrices
+// Hp = A + Bz, Hm = A - Bz, Bx, By (and S when k != 0) instead of the complex
+// 2n x 2n matrix: half the bytes, and 12 instead of 16 real MFMAs per complex
+// multiply-add block at Gamma.  Matrices are stored pre-tiled in MFMA
+// A-operand order: [cell][row block of 16][k-step of 4][matrix][64 lanes].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace chfsi {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class T> struct Vec4;
+template <> struct Vec4<double> { typedef d4 type; };
+template <> struct Vec4<float> { typedef f4 type; };
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+#define LAUNCH_CHECK() CHFSI_HIP(hipGetLastError())
+
+// ============================================================================
+// Cell operator setup
+// ============================================================================
+// One block per (cell, row block of 16).  Weighted masses by quadrature,
+//   M_f[i][j] = sum_q w_q J f(r_q) N_i(r_q) N_j(r_q),  N_i = l_ax l_ay l_az,
+// for f in {V, Bx, By, Bz}; then the scaled Pauli-form matrices.
+__global__ __launch_bounds__(256) void cell_setup_kernel(
+    const double* __restrict__ V, const double* __restrict__ B, const double* __restrict__ U0,
+    const double* __restrict__ Sk, const double* __restrict__ minv_sqrt,
+    const int32_t* __restrict__ cell_nodes, const double* __restrict__ B1,
+    const double* __restrict__ wq1, double J, int np1, int nq, int nloc, int nrb, int nkb, int nmat,
+    double* __restrict__ out) {
+  extern __shared__ double smem[];
+  const int nq3 = nq * nq * nq;
+  double* sW = smem;                 // [4][nq3]
+  double* sB1 = sW + 4 * nq3;        // [np1][nq]
+  double* sS = sB1 + np1 * nq;       // [nloc] M^{-1/2} at the cell's nodes
+  const int e = blockIdx.x, rb = blockIdx.y;
+  for (int q = threadIdx.x; q < nq3; q += blockDim.x) {
+    const int qx = q % nq, qy = (q / nq) % nq, qz = q / (nq * nq);
+    const double wJ = wq1[qx] * wq1[qy] * wq1[qz] * J;
+    sW[q] = wJ * V[(size_t)e * nq3 + q];
+    for (int d = 0; d < 3; ++d) sW[(d + 1) * nq3 + q] = wJ * B[((size_t)e * nq3 + q) * 3 + d];
+  }
+  for (int t = threadIdx.x; t < np1 * nq; t += blockDim.x) sB1[t] = B1[t];
+  for (int a = threadIdx.x; a < nloc; a += blockDim.x)
+    sS[a] = minv_sqrt[cell_nodes[(size_t)e * nloc + a]];
+  __syncthreads();
+  const int npad = nkb * 4;
+  for (int t = threadIdx.x; t < 16 * npad; t += blockDim.x) {
+    const int il = t % 16, j = t / 16;
+    const int i = rb * 16 + il;
+    double mv = 0.0, mbx = 0.0, mby = 0.0, mbz = 0.0;
+    const bool valid = (i < nloc) && (j < nloc);
+    if (valid) {
+      const int ax = i % np1, ay = (i / np1) % np1, az = i / (np1 * np1);
+      const int bx = j % np1, by = (j / np1) % np1, bz = j / (np1 * np1);
+      for (int qz = 0; qz < nq; ++qz) {
+        const double ez = sB1[az * nq + qz] * sB1[bz * nq + qz];
+        for (int qy = 0; qy < nq; ++qy) {
+          const double eyz = ez * sB1[ay * nq + qy] * sB1[by * nq + qy];
+          const int qb = nq * (qy + nq * qz);
+          for (int qx = 0; qx < nq; ++qx) {
+            const double ev = eyz * sB1[ax * nq + qx] * sB1[bx * nq + qx];
+            const int q = qb + qx;
+            mv += ev * sW[q];
+            mbx += ev * sW[nq3 + q];
+            mby += ev * sW[2 * nq3 + q];
+            mbz += ev * sW[3 * nq3 + q];
+          }
+        }
+      }
+    }
+    double vals[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      const double s = sS[i] * sS[j];
+      const double a0 = U0[(size_t)i * nloc + j] + mv;
+      vals[0] = s * (a0 + mbz);
+      vals[1] = s * (a0 - mbz);
+      vals[2] = s * mbx;
+      vals[3] = s * mby;
+      vals[4] = (nmat > 4) ? s * Sk[(size_t)i * nloc + j] : 0.0;
+    }
+    const int kb = j / 4, lane = (j % 4) * 16 + il;
+    double* dst = out + (((size_t)e * nrb + rb) * nkb + kb) * nmat * 64 + lane;
+    for (int m = 0; m < nmat; ++m) dst[m * 64] = vals[m];
+  }
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+void launch_cell_setup(chfsi_ctx* c, KPoint& kp, const double* V, const double* B, const double* U0,
+                       const double* S) {
+  const size_t per_cell = (size_t)c->nrb * c->nkb * kp.nmat * 64;
+  kp.cell64.alloc(per_cell * c->n_cells);
+  DevBuf<double> b1, wq;
+  b1.upload(c->ref.B.data(), c->ref.B.size(), c->stream);
+  wq.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
+  const size_t sh = (4 * (size_t)c->nq3 + c->np1 * c->nq + c->nloc) * sizeof(double);
+  dim3 grid(c->n_cells, c->nrb);
+  hipLaunchKernelGGL(cell_setup_kernel, grid, dim3(256), sh, c->stream, V, B, U0, S, c->minv_sqrt.ptr,
+                     c->cell_nodes.ptr, b1.ptr, wq.ptr, c->J, c->np1, c->nq, c->nloc, c->nrb, c->nkb,
+                     kp.nmat, kp.cell64.ptr);
+  LAUNCH_CHECK();
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+}
+
+void launch_cell_to_f32(chfsi_ctx* c, KPoint& kp) {
+  const size_t n = kp.cell64.n;
+  kp.cell32.alloc(n);
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(4096), dim3(256), 0, c->stream, kp.cell64.ptr, kp.cell32.ptr, n);
+  LAUNCH_CHECK();
+}
+
+// ============================================================================
+// Fused gather / cell product / scatter-add, one launch per colour
+// ============================================================================
+// Block = 4 waves as 2 (row blocks) x 2 (column halves).  Block tile: 32 local
+// rows x BN = 32*CB columns of one cell.  K loop over the cell's local nodes in
+// stages of 8 nodes: the gathered spinor rows (X_up = a + ib, X_dn = c + id)
+// are staged in LDS as four planar real arrays, double-buffered, with the
+// next stage's global loads issued before the current stage's MFMAs.  Each
+// wave reads its A fragments (Hp, Hm, Bx, By, S) straight from the pre-tiled
+// cell operator.  Per 4-node k-step and 16-column block the products are
+//   Yup_r += Hp a + Bx c + By d - S b      Yup_i += Hp b + Bx d - By c + S a
+//   Ydn_r += Hm c + Bx a - By b - S d      Ydn_i += Hm d + Bx b + By a + S c
+template <class T, int CB, bool HAS_S>
+__global__ __launch_bounds__(256) void cell_apply_kernel(
+    const T* __restrict__ cm, const int32_t* __restrict__ cell_nodes,
+    const int32_t* __restrict__ cells, int nloc, int nrb, int nkb, int nmat, int n_rowtiles,
+    int n_coltiles, const double2* __restrict__ X, int64_t ldx, double2* __restrict__ W, int64_t ldw,
+    int n_vec, double alpha) {
+  typedef typename Vec4<T>::type V4;
+  constexpr int BN = 32 * CB;
+  constexpr int BK = 8;
+  constexpr int NPRE = (BK * 2 * BN) / 256;
+  __shared__ T sB[2][4][BK][BN];
+  __shared__ int32_t sNode[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
+
+  const int tid = threadIdx.x;
+  const int bid = blockIdx.x;
+  const int ct = bid % n_coltiles;
+  const int rt = (bid / n_coltiles) % n_rowtiles;
+  const int ci = bid / (n_coltiles * n_rowtiles);
+  const int e = cells[ci];
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int rb = rt * 2 + wr;
+  const bool row_active = rb < nrb;
+  const int col0 = ct * BN;
+
+  for (int i = tid; i < nloc; i += 256) sNode[i] = cell_nodes[(size_t)e * nloc + i];
+  __syncthreads();
+
+  V4 acc[CB][4];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[cb][k] = V4{0, 0, 0, 0};
+
+  const T* Abase = cm + ((size_t)(e * nrb + (row_active ? rb : 0)) * nkb) * nmat * 64 + lane;
+  const int nstage = nkb / 2;
+  double2 pre[NPRE];
+
+  auto gload = [&](int s) {
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) {
+      const int idx = tid + 256 * j;
+      const int col = idx % BN, sp = (idx / BN) & 1, kk = idx / (2 * BN);
+      const int knode = s * BK + kk;
+      const int gcol = col0 + col;
+      double2 v = {0.0, 0.0};
+      if (knode < nloc && gcol < n_vec) v = X[(2 * (int64_t)sNode[knode] + sp) * ldx + gcol];
+      pre[j] = v;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) {
+      const int idx = tid + 256 * j;
+      const int col = idx % BN, sp = (idx / BN) & 1, kk = idx / (2 * BN);
+      sB[buf][2 * sp][kk][col] = (T)pre[j].x;
+      sB[buf][2 * sp + 1][kk][col] = (T)pre[j].y;
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstage) gload(s + 1);
+    if (row_active) {
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const T* Ap = Abase + (size_t)(s * 2 + kk) * nmat * 64;
+        const T hp = Ap[0], hm = Ap[64], bx = Ap[128], by = Ap[192];
+        const T sv = HAS_S ? Ap[256] : (T)0;
+        const T nby = -by, nsv = -sv;
+        const int krow = kk * 4 + (lane >> 4);
+        T ba[CB], bb[CB], bc[CB], bd[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int col = wc * (CB * 16) + cb * 16 + (lane & 15);
+          ba[cb] = sB[buf][0][krow][col];
+          bb[cb] = sB[buf][1][krow][col];
+          bc[cb] = sB[buf][2][krow][col];
+          bd[cb] = sB[buf][3][krow][col];
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          acc[cb][0] = mfma(hp, ba[cb], acc[cb][0]);
+          acc[cb][1] = mfma(hp, bb[cb], acc[cb][1]);
+          acc[cb][2] = mfma(hm, bc[cb], acc[cb][2]);
+          acc[cb][3] = mfma(hm, bd[cb], acc[cb][3]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          acc[cb][0] = mfma(bx, bc[cb], acc[cb][0]);
+          acc[cb][1] = mfma(bx, bd[cb], acc[cb][1]);
+          acc[cb][2] = mfma(bx, ba[cb], acc[cb][2]);
+          acc[cb][3] = mfma(bx, bb[cb], acc[cb][3]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          acc[cb][0] = mfma(by, bd[cb], acc[cb][0]);
+          acc[cb][1] = mfma(nby, bc[cb], acc[cb][1]);
+          acc[cb][2] = mfma(nby, bb[cb], acc[cb][2]);
+          acc[cb][3] = mfma(by, ba[cb], acc[cb][3]);
+        }
+        if (HAS_S) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            acc[cb][0] = mfma(nsv, bb[cb], acc[cb][0]);
+            acc[cb][1] = mfma(sv, ba[cb], acc[cb][1]);
+            acc[cb][2] = mfma(nsv, bd[cb], acc[cb][2]);
+            acc[cb][3] = mfma(sv, bc[cb], acc[cb][3]);
+          }
+        }
+      }
+    }
+    if (s + 1 < nstage) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  if (!row_active) return;
+  // epilogue: lane holds rows 4*(lane/16)+j, column lane%16 of each 16x16 tile
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int rl = rb * 16 + 4 * (lane >> 4) + j;
+    if (rl >= nloc) continue;
+    const int64_t node = sNode[rl];
+    double2* w0 = W + (2 * node) * ldw;
+    double2* w1 = W + (2 * node + 1) * ldw;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int gcol = col0 + wc * (CB * 16) + cb * 16 + (lane & 15);
+      if (gcol >= n_vec) continue;
+      double2 o0 = w0[gcol], o1 = w1[gcol];
+      o0.x += alpha * (double)acc[cb][0][j];
+      o0.y += alpha * (double)acc[cb][1][j];
+      o1.x += alpha * (double)acc[cb][2][j];
+      o1.y += alpha * (double)acc[cb][3][j];
+      w0[gcol] = o0;
+      w1[gcol] = o1;
+    }
+  }
+}
+
+template <class T, int CB, bool HAS_S>
+static void launch_cells(chfsi_ctx* c, const T* cm, int nmat, const double2* X, int64_t ldx,
+                         double2* W, int64_t ldw, int n_vec, double alpha) {
+  const int BN = 32 * CB;
+  const int n_rowtiles = cdiv(c->nrb, 2);
+  const int n_coltiles = cdiv(n_vec, BN);
+  for (int k = 0; k < c->n_colours; ++k) {
+    const int n_in = c->colour_off[k + 1] - c->colour_off[k];
+    if (n_in == 0) continue;
+    const int nblk = n_in * n_rowtiles * n_coltiles;
+    const double n2 = 2.0 * c->nloc;
+    const double flops = 8.0 * n2 * n2 * n_vec * n_in;
+    // issued MFMA flops: per cell nrb row blocks x 2 column waves per column tile,
+    // each nkb k-steps of CB x (12 | 16) MFMAs of 16x16x4 (2048 flops)
+    const double exec = (double)n_in * c->nrb * 2.0 * n_coltiles * c->nkb * CB * (HAS_S ? 16 : 12) * 2048.0;
+    const double bytes = (double)n_in * ((double)nmat * c->nloc * c->nloc * sizeof(T) +
+                                         3.0 * c->nloc * 2.0 * n_vec * sizeof(double2));
+    StageTimer tm(c, sizeof(T) == 8 ? CHFSI_STAGE_CELL_FP64 : CHFSI_STAGE_CELL_FP32, flops, exec, bytes);
+    hipLaunchKernelGGL((cell_apply_kernel<T, CB, HAS_S>), dim3(nblk), dim3(256), 0, c->stream, cm,
+                       c->cell_nodes.ptr, c->colour_cells.ptr + c->colour_off[k], c->nloc, c->nrb,
+                       c->nkb, nmat, n_rowtiles, n_coltiles, X, ldx, W, ldw, n_vec, alpha);
+    LAUNCH_CHECK();
+  }
+}
+
+template <class T, bool HAS_S>
+static void launch_cells_cb(chfsi_ctx* c, const T* cm, int nmat, const double2* X, int64_t ldx,
+                            double2* W, int64_t ldw, int n_vec, double alpha) {
+  if (n_vec > 64)
+    launch_cells<T, 4, HAS_S>(c, cm, nmat, X, ldx, W, ldw, n_vec, alpha);
+  else if (n_vec > 32)
+    launch_cells<T, 2, HAS_S>(c, cm, nmat, X, ldx, W, ldw, n_vec, alpha);
+  else
+    launch_cells<T, 1, HAS_S>(c, cm, nmat, X, ldx, W, ldw, n_vec, alpha);
+}
+
+// ============================================================================
+// Element-wise passes
+// ============================================================================
+__global__ void axpby_rows_kernel(double2* __restrict__ W, int64_t ldw, const double2* __restrict__ X,
+                                  int64_t ldx, int64_t rows, int n_vec, double beta, double gamma) {
+  const int64_t total = rows * n_vec;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / n_vec;
+    const int n = (int)(t - r * n_vec);
+    double2 w = {0.0, 0.0};
+    if (beta != 0.0) {
+      w = W[r * ldw + n];
+      w.x *= beta;
+      w.y *= beta;
+    }
+    if (gamma != 0.0) {
+      const double2 x = X[r * ldx + n];
+      w.x += gamma * x.x;
+      w.y += gamma * x.y;
+    }
+    W[r * ldw + n] = w;
+  }
+}
+
+void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,
+                       int64_t rows, int n_vec, double beta, double gamma) {
+  const int64_t total = rows * n_vec;
+  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0,
+                (double)total * sizeof(double2) * (1.0 + (beta != 0.0) + (gamma != 0.0)));
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+  hipLaunchKernelGGL(axpby_rows_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, c->stream, W, ldw, X,
+                     ldx, rows, n_vec, beta, gamma);
+  LAUNCH_CHECK();
+}
+
+__global__ void copy_rows_kernel(double2* __restrict__ D, int64_t ldd, const double2* __restrict__ S,
+                                 int64_t lds, int64_t rows, int n_vec) {
+  const int64_t total = rows * n_vec;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / n_vec;
+    const int n = (int)(t - r * n_vec);
+    D[r * ldd + n] = S[r * lds + n];
+  }
+}
+
+void launch_copy_rows(chfsi_ctx* c, double2* dst, int64_t ldd, const double2* src, int64_t lds,
+                      int64_t rows, int n_vec) {
+  const int64_t total = rows * n_vec;
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, c->stream, dst, ldd, src,
+                     lds, rows, n_vec);
+  LAUNCH_CHECK();
+}
+
+// ============================================================================
+// Nonlocal projector terms (eqn:FEHnloc in the cell form of Sec. IV.B)
+// ============================================================================
+template <class T> struct C2;
+template <> struct C2<double> { typedef double2 type; };
+template <> struct C2<float> { typedef float2 type; };
+
+constexpr int kMaxPj = 9;
+
+// Partial C[2 chi + s][n] over one chunk of an atom's support nodes:
+// sum_j conj(P[j][chi]) X[2 node_j + s][n].  Block: 64 columns x 2 spins.
+template <class T>
+__global__ __launch_bounds__(128) void nl_project_kernel(
+    const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ sup_node,
+    const int32_t* __restrict__ chunk_atom, const int32_t* __restrict__ chunk_begin,
+    const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ atom_npj, int max_pj,
+    const double2* __restrict__ X, int64_t ldx, int n_vec, typename C2<T>::type* __restrict__ partial) {
+  typedef typename C2<T>::type CT;
+  __shared__ CT sP[kNlChunk * kMaxPj];
+  __shared__ int32_t sN[kNlChunk];
+  const int ch = blockIdx.x;
+  const int a = chunk_atom[ch], b = chunk_begin[ch], e = chunk_end[ch];
+  const int npj = atom_npj[a];
+  const int cnt = e - b;
+  for (int t = threadIdx.x; t < cnt * max_pj; t += blockDim.x) sP[t] = proj[(size_t)b * max_pj + t];
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) sN[t] = sup_node[b + t];
+  __syncthreads();
+  const int col = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int sp = threadIdx.x >> 6;
+  T ar[kMaxPj], ai[kMaxPj];
+#pragma unroll
+  for (int x = 0; x < kMaxPj; ++x) ar[x] = ai[x] = (T)0;
+  if (col < n_vec) {
+    for (int j = 0; j < cnt; ++j) {
+      const double2 xv = X[(2 * (int64_t)sN[j] + sp) * ldx + col];
+      const T xr = (T)xv.x, xi = (T)xv.y;
+#pragma unroll
+      for (int x = 0; x < kMaxPj; ++x) {
+        if (x < npj) {
+          const CT p = sP[j * max_pj + x];
+          ar[x] += p.x * xr + p.y * xi;     // conj(p) * x
+          ai[x] += p.x * xi - p.y * xr;
+        }
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < kMaxPj; ++x) {
+      if (x < max_pj) {
+        CT v;
+        v.x = ar[x];
+        v.y = ai[x];
+        partial[((size_t)ch * 2 * max_pj + 2 * x + sp) * n_vec + col] = v;
+      }
+    }
+  }
+}
+
+// C'[a][r][n] = alpha sum_r' Delta_a[r][r'] sum_{chunks of a} partial[chunk][r'][n]
+template <class T>
+__global__ __launch_bounds__(64) void nl_couple_kernel(
+    const typename C2<T>::type* __restrict__ partial, const int32_t* __restrict__ atom_chunk0,
+    const int32_t* __restrict__ atom_npj, const double2* __restrict__ delta, int max_pj, int n_vec,
+    double alpha, typename C2<T>::type* __restrict__ Cp) {
+  typedef typename C2<T>::type CT;
+  const int a = blockIdx.x;
+  const int col = blockIdx.y * 64 + threadIdx.x;
+  if (col >= n_vec) return;
+  const int nr = 2 * atom_npj[a];
+  const int mr = 2 * max_pj;
+  T cr[2 * kMaxPj], cim[2 * kMaxPj];
+#pragma unroll
+  for (int r = 0; r < 2 * kMaxPj; ++r) cr[r] = cim[r] = (T)0;
+  for (int ch = atom_chunk0[a]; ch < atom_chunk0[a + 1]; ++ch)
+#pragma unroll
+    for (int r = 0; r < 2 * kMaxPj; ++r)
+      if (r < nr) {
+        const CT v = partial[((size_t)ch * mr + r) * n_vec + col];
+        cr[r] += v.x;
+        cim[r] += v.y;
+      }
+  for (int r = 0; r < mr; ++r) {
+    T sr = 0, si = 0;
+    if (r < nr) {
+#pragma unroll
+      for (int q = 0; q < 2 * kMaxPj; ++q)
+        if (q < nr) {
+          const double2 d = delta[((size_t)a * mr + r) * mr + q];
+          sr += (T)d.x * cr[q] - (T)d.y * cim[q];
+          si += (T)d.x * cim[q] + (T)d.y * cr[q];
+        }
+    }
+    CT o;
+    o.x = (T)alpha * sr;
+    o.y = (T)alpha * si;
+    Cp[((size_t)a * mr + r) * n_vec + col] = o;
+  }
+}
+
+// W[2 node + s][n] += sum_{(entry, atom) at node} sum_chi P[entry][chi] C'[atom][2 chi + s][n];
+// one wave per node, deterministic order of the (entry, atom) list.
+template <class T>
+__global__ __launch_bounds__(256) void nl_scatter_kernel(
+    const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ unode,
+    const int32_t* __restrict__ unode_off, const int32_t* __restrict__ ulist_entry,
+    const int32_t* __restrict__ ulist_atom, const int32_t* __restrict__ atom_npj, int max_pj,
+    int64_t n_unodes, const typename C2<T>::type* __restrict__ Cp, int n_vec, double2* __restrict__ W,
+    int64_t ldw) {
+  typedef typename C2<T>::type CT;
+  const int64_t un = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (un >= n_unodes) return;
+  const int64_t node = unode[un];
+  const int l0 = unode_off[un], l1 = unode_off[un + 1];
+  const int mr = 2 * max_pj;
+  for (int col = lane; col < n_vec; col += 64) {
+    T r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+    for (int t = l0; t < l1; ++t) {
+      const int ent = ulist_entry[t], a = ulist_atom[t];
+      const int npj = atom_npj[a];
+      for (int x = 0; x < npj; ++x) {
+        const CT p = proj[(size_t)ent * max_pj + x];
+        const CT c0 = Cp[((size_t)a * mr + 2 * x) * n_vec + col];
+        const CT c1 = Cp[((size_t)a * mr + 2 * x + 1) * n_vec + col];
+        r0 += p.x * c0.x - p.y * c0.y;
+        i0 += p.x * c0.y + p.y * c0.x;
+        r1 += p.x * c1.x - p.y * c1.y;
+        i1 += p.x * c1.y + p.y * c1.x;
+      }
+    }
+    double2* w0 = W + (2 * node) * ldw + col;
+    double2* w1 = W + (2 * node + 1) * ldw + col;
+    double2 o0 = *w0, o1 = *w1;
+    o0.x += (double)r0;
+    o0.y += (double)i0;
+    o1.x += (double)r1;
+    o1.y += (double)i1;
+    *w0 = o0;
+    *w1 = o1;
+  }
+}
+
+template <class T>
+static void nonlocal_apply(chfsi_ctx* c, NonlocalK& nl, const typename C2<T>::type* proj,
+                           const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
+                           double alpha) {
+  typedef typename C2<T>::type CT;
+  if (nl.n_atoms == 0 || nl.n_entries == 0) return;
+  const int mr = 2 * nl.max_pj;
+  const size_t n_part = (size_t)nl.n_chunks * mr * n_vec;
+  const size_t n_cp = (size_t)nl.n_atoms * mr * n_vec;
+  const size_t bytes = (n_part + n_cp) * sizeof(CT);
+  c->scratch.alloc((bytes + sizeof(double) - 1) / sizeof(double));
+  CT* partial = reinterpret_cast<CT*>(c->scratch.ptr);
+  CT* Cp = partial + n_part;
+  const int nct = cdiv(n_vec, 64);
+  double nl_flops = 0.0;
+  for (const auto& at : nl.atoms)
+    nl_flops += 2.0 * 8.0 * at.n_sup * at.n_pj * 2.0 * n_vec + 8.0 * 4.0 * at.n_pj * at.n_pj * n_vec;
+  const double nl_bytes = (double)nl.n_entries * (2.0 * n_vec * sizeof(double2) + nl.max_pj * sizeof(CT)) +
+                          (double)nl.n_unodes * 2.0 * 2.0 * n_vec * sizeof(double2);
+  StageTimer tm(c, CHFSI_STAGE_NONLOCAL, nl_flops, nl_flops, nl_bytes);
+  hipLaunchKernelGGL(nl_project_kernel<T>, dim3(nl.n_chunks, nct), dim3(128), 0, c->stream, proj,
+                     nl.sup_node.ptr, nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr,
+                     nl.atom_npj.ptr, nl.max_pj, X, ldx, n_vec, partial);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(nl_couple_kernel<T>, dim3(nl.n_atoms, nct), dim3(64), 0, c->stream, partial,
+                     nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.delta.ptr, nl.max_pj, n_vec, alpha, Cp);
+  LAUNCH_CHECK();
+  const int nb = cdiv(nl.n_unodes, 4);
+  hipLaunchKernelGGL(nl_scatter_kernel<T>, dim3(nb), dim3(256), 0, c->stream, proj, nl.unode.ptr,
+                     nl.unode_off.ptr, nl.ulist_entry.ptr, nl.ulist_atom.ptr, nl.atom_npj.ptr,
+                     nl.max_pj, nl.n_unodes, Cp, n_vec, W, ldw);
+  LAUNCH_CHECK();
+}
+
+void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+             int n_vec, int prec, double alpha, double beta, double gamma) {
+  const int64_t rows = 2 * c->n_nodes;
+  launch_axpby_rows(c, W, ldw, X, ldx, rows, n_vec, beta, gamma);
+  if (prec == CHFSI_PREC_MIXED) {
+    nonlocal_apply<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, W, ldw, n_vec, alpha);
+    if (kp.gamma)
+      launch_cells_cb<float, false>(c, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
+    else
+      launch_cells_cb<float, true>(c, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
+  } else {
+    nonlocal_apply<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, W, ldw, n_vec, alpha);
+    if (kp.gamma)
+      launch_cells_cb<double, false>(c, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
+    else
+      launch_cells_cb<double, true>(c, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
+  }
+}
+
+// ============================================================================
+// Dense tall-skinny products (FP64 MFMA) for CholGS and Rayleigh-Ritz
+// ============================================================================
+// Partial S = X^H Y over a chunk of rows.  Wave tile 32 x 32 complex
+// (2 x 2 MFMA blocks), block = 4 waves = 64 x 64 tile.  Fragments come straight
+// from global memory: A[i][k] = X[row k][col i], B[k][j] = Y[row k][col j].
+__global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X, int64_t ldx,
+                                                   const double2* __restrict__ Y, int64_t ldy,
+                                                   int64_t rows, int n, int64_t chunk_rows,
+                                                   const int2* __restrict__ tiles,
+                                                   double2* __restrict__ partial) {
+  const int2 tl = tiles[blockIdx.x];
+  const int chunk = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = tl.x * 64 + (wave & 1) * 32, j0 = tl.y * 64 + (wave >> 1) * 32;
+  const int64_t r_begin = chunk * chunk_rows;
+  const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
+  d4 sr[2][2], si[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) sr[a][b] = si[a][b] = d4{0, 0, 0, 0};
+  const int kl = lane >> 4, il = lane & 15;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += 4) {
+    const int64_t r = r0 + kl;
+    double2 xa[2], yb[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int ci = i0 + a * 16 + il, cj = j0 + a * 16 + il;
+      xa[a] = (r < r_end && ci < n) ? X[r * ldx + ci] : double2{0.0, 0.0};
+      yb[a] = (r < r_end && cj < n) ? Y[r * ldy + cj] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double nxi = -xa[a].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        sr[a][b] = mfma(xa[a].x, yb[b].x, sr[a][b]);
+        sr[a][b] = mfma(xa[a].y, yb[b].y, sr[a][b]);
+        si[a][b] = mfma(xa[a].x, yb[b].y, si[a][b]);
+        si[a][b] = mfma(nxi, yb[b].x, si[a][b]);
+      }
+    }
+  }
+  double2* out = partial + (size_t)chunk * n * n;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ri = i0 + a * 16 + 4 * (lane >> 4) + j;
+        const int cj = j0 + b * 16 + (lane & 15);
+        if (ri < n && cj < n) out[(size_t)ri * n + cj] = double2{sr[a][b][j], si[a][b][j]};
+      }
+}
+
+__global__ void gram_reduce_kernel(const double2* __restrict__ partial, int n_chunks, int n,
+                                   const int2* __restrict__ tiles, double2* __restrict__ S) {
+  const int2 tl = tiles[blockIdx.x];
+  for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) {
+    const int i = tl.x * 64 + t / 64, j = tl.y * 64 + t % 64;
+    if (i >= n || j >= n) continue;
+    double2 s = {0.0, 0.0};
+    for (int c = 0; c < n_chunks; ++c) {
+      const double2 v = partial[((size_t)c * n + i) * n + j];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    S[(size_t)i * n + j] = s;
+  }
+}
+
+void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t ldy, int64_t rows,
+          int n, std::vector<cplx>& S, bool lower_only) {
+  const int nt = cdiv(n, 64);
+  std::vector<int2> tiles;
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j < nt; ++j)
+      if (!lower_only || j <= i) tiles.push_back(int2{i, j});
+  const int ntl = (int)tiles.size();
+  int n_chunks = std::max(1, std::min<int>(2048 / ntl, cdiv(rows, 256)));
+  int64_t chunk_rows = (rows + n_chunks - 1) / n_chunks;
+  chunk_rows = (chunk_rows + 3) / 4 * 4;
+  n_chunks = cdiv(rows, chunk_rows);
+  const size_t need = (size_t)n_chunks * n * n + (size_t)n * n;   // double2 units
+  c->scratch.alloc(2 * need + ntl);                               // + tiles (int2 = 1 double)
+  double2* partial = reinterpret_cast<double2*>(c->scratch.ptr);
+  double2* Sd = partial + (size_t)n_chunks * n * n;
+  int2* td = reinterpret_cast<int2*>(Sd + (size_t)n * n);
+  CHFSI_HIP(hipMemcpyAsync(td, tiles.data(), ntl * sizeof(int2), hipMemcpyHostToDevice, c->stream));
+  StageTimer tm(c, CHFSI_STAGE_GRAM, 8.0 * (double)rows * n * n * ((double)ntl / (nt * nt)),
+                8.0 * (double)rows * 4096.0 * ntl, 2.0 * (double)rows * n * sizeof(double2));
+  hipLaunchKernelGGL(gram_kernel, dim3(ntl, n_chunks), dim3(256), 0, c->stream, X, ldx, Y, ldy, rows, n,
+                     chunk_rows, td, partial);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(ntl), dim3(256), 0, c->stream, partial, n_chunks, n, td, Sd);
+  LAUNCH_CHECK();
+  std::vector<double2> h((size_t)n * n);
+  CHFSI_HIP(hipMemcpyAsync(h.data(), Sd, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  S.resize((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (lower_only && j > i)
+        S[(size_t)i * n + j] = std::conj(cplx(h[(size_t)j * n + i].x, h[(size_t)j * n + i].y));
+      else
+        S[(size_t)i * n + j] = cplx(h[(size_t)i * n + j].x, h[(size_t)i * n + j].y);
+    }
+}
+
+// X[r0 + r][:] = P[r][:] Q over a row panel P (a copy of those rows).  Wave tile
+// 32 rows x 32 columns complex, block 64 x 64.  upper: Q[k][j] = 0 for k > j.
+__global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__ P, int n,
+                                                     int64_t prow, const double2* __restrict__ Q,
+                                                     double2* __restrict__ X, int64_t ldx, int upper) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t rbase = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  const int j0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int kend = upper ? std::min(n, (int)(blockIdx.y * 64 + 64)) : n;
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = d4{0, 0, 0, 0};
+  const int kl = lane >> 4, il = lane & 15;
+  for (int k0 = 0; k0 < kend; k0 += 4) {
+    const int k = k0 + kl;
+    double2 xa[2], qb[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int64_t r = rbase + a * 16 + il;
+      xa[a] = (r < prow && k < n) ? P[r * n + k] : double2{0.0, 0.0};
+      const int cj = j0 + a * 16 + il;
+      qb[a] = (k < n && cj < n) ? Q[(size_t)k * n + cj] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double nxi = -xa[a].y;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = mfma(xa[a].x, qb[b].x, cr[a][b]);
+        cr[a][b] = mfma(nxi, qb[b].y, cr[a][b]);
+        ci[a][b] = mfma(xa[a].x, qb[b].y, ci[a][b]);
+        ci[a][b] = mfma(xa[a].y, qb[b].x, ci[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t r = rbase + a * 16 + 4 * (lane >> 4) + j;
+        const int cj = j0 + b * 16 + (lane & 15);
+        if (r < prow && cj < n) X[r * ldx + cj] = double2{cr[a][b][j], ci[a][b][j]};
+      }
+}
+
+void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n, const std::vector<cplx>& Q,
+                    bool upper) {
+  // panel of rows copied to scratch, then multiplied back into place
+  int64_t prow = std::max<int64_t>(64, ((int64_t)1 << 27) / ((int64_t)n * 16));   // <= 128 MiB
+  prow = std::min<int64_t>(prow, rows);
+  prow = (prow + 63) / 64 * 64;
+  c->panel.alloc((size_t)prow * n * 2 + (size_t)n * n * 2);
+  double2* P = reinterpret_cast<double2*>(c->panel.ptr);
+  double2* Qd = P + (size_t)prow * n;
+  std::vector<double2> qh((size_t)n * n);
+  for (size_t i = 0; i < qh.size(); ++i) qh[i] = double2{Q[i].real(), Q[i].imag()};
+  CHFSI_HIP(hipMemcpyAsync(Qd, qh.data(), qh.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+  StageTimer tm(c, CHFSI_STAGE_ROTATE, 8.0 * (double)rows * n * n * (upper ? 0.5 : 1.0),
+                8.0 * (double)rows * n * n, 4.0 * (double)rows * n * sizeof(double2));
+  for (int64_t r0 = 0; r0 < rows; r0 += prow) {
+    const int64_t pr = std::min(prow, rows - r0);
+    launch_copy_rows(c, P, n, X + r0 * ldx, ldx, pr, n);
+    dim3 grid(cdiv(pr, 64), cdiv(n, 64));
+    hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, c->stream, P, n, pr, Qd, X + r0 * ldx, ldx,
+                       upper ? 1 : 0);
+    LAUNCH_CHECK();
+  }
+  CHFSI_HIP(hipStreamSynchronize(c->stream));   // qh leaves scope
+}
+
+// ============================================================================
+// Reductions with a fixed grid (deterministic order)
+// ============================================================================
+constexpr int kRedGroups = 256;
+
+__global__ __launch_bounds__(256) void resid_kernel(const double2* __restrict__ W, int64_t ldw,
+                                                    const double2* __restrict__ X, int64_t ldx,
+                                                    int64_t rows, int n, const double* __restrict__ theta,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int g = blockIdx.x;
+  const int col = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int lr = threadIdx.x >> 6;
+  double s = 0.0;
+  if (col < n) {
+    const double th = theta[col];
+    for (int64_t r = (int64_t)g * 4 + lr; r < rows; r += (int64_t)kRedGroups * 4) {
+      const double2 w = W[r * ldw + col], x = X[r * ldx + col];
+      const double dr = w.x - th * x.x, di = w.y - th * x.y;
+      s += dr * dr + di * di;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < 64 && col < n)
+    partial[(size_t)g * n + col] = ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) +
+                                   red[threadIdx.x + 192];
+}
+
+void column_resid_norms(chfsi_ctx* c, const double2* W, int64_t ldw, const double2* X, int64_t ldx,
+                        int64_t rows, int n, const double* theta, double* out) {
+  c->scratch.alloc((size_t)kRedGroups * n + n);
+  double* part = c->scratch.ptr;
+  double* th = part + (size_t)kRedGroups * n;
+  CHFSI_HIP(hipMemcpyAsync(th, theta, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(resid_kernel, dim3(kRedGroups, cdiv(n, 64)), dim3(256), 0, c->stream, W, ldw, X, ldx,
+                     rows, n, th, part);
+  LAUNCH_CHECK();
+  std::vector<double> h((size_t)kRedGroups * n);
+  CHFSI_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    for (int g = 0; g < kRedGroups; ++g) s += h[(size_t)g * n + j];
+    out[j] = std::sqrt(s);
+  }
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(const double2* __restrict__ x, const double2* __restrict__ y,
+                                                  int64_t rows, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t r = blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)kRedGroups * 256)
+    s += x[r].x * y[r].x + x[r].y * y[r].y;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+double dot_re(chfsi_ctx* c, const double2* x, const double2* y, int64_t rows) {
+  c->scratch.alloc(kRedGroups);
+  hipLaunchKernelGGL(dot_kernel, dim3(kRedGroups), dim3(256), 0, c->stream, x, y, rows, c->scratch.ptr);
+  LAUNCH_CHECK();
+  double h[kRedGroups];
+  CHFSI_HIP(hipMemcpyAsync(h, c->scratch.ptr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (int g = 0; g < kRedGroups; ++g) s += h[g];
+  return s;
+}
+
+// ============================================================================
+// Seeded fill (SplitMix64, counter form) and finiteness check
+// ============================================================================
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void fill_random_kernel(double2* __restrict__ X, int64_t n_rows, int n_vec, int64_t ld,
+                                   uint64_t seed, int64_t row0, int col0, int64_t ntc) {
+  const int64_t total = n_rows * n_vec;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / n_vec;
+    const int n = (int)(t - r * n_vec);
+    const uint64_t j = (uint64_t)(row0 + r) * (uint64_t)ntc + (uint64_t)(col0 + n);
+    const double ur = (double)(splitmix64_at(seed, 2 * j) >> 11) * (1.0 / 9007199254740992.0);
+    const double ui = (double)(splitmix64_at(seed, 2 * j + 1) >> 11) * (1.0 / 9007199254740992.0);
+    X[r * ld + n] = double2{2.0 * ur - 1.0, 2.0 * ui - 1.0};
+  }
+}
+
+void launch_fill_random(chfsi_ctx* c, double2* X, int64_t n_rows, int n_vec, int64_t ld, uint64_t seed,
+                        int64_t row0, int col0, int64_t ntc) {
+  const int64_t total = n_rows * n_vec;
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+  hipLaunchKernelGGL(fill_random_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, c->stream, X, n_rows,
+                     n_vec, ld, seed, row0, col0, ntc);
+  LAUNCH_CHECK();
+}
+
+__global__ void zero_int_kernel(int* __restrict__ f) { f[0] = 0; }
+
+__global__ void nonfinite_kernel(const double* __restrict__ p, int64_t n, int* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(p[i])) flag[0] = 1;
+}
+
+int check_finite(chfsi_ctx* c, const double* p, int64_t n) {
+  c->scratch.alloc(1);
+  int* flag = reinterpret_cast<int*>(c->scratch.ptr);
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, c->stream, flag);
+  LAUNCH_CHECK();
+  const int blocks = (int)std::min<int64_t>(cdiv(n, 256), 4096);
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, c->stream, p, n, flag);
+  LAUNCH_CHECK();
+  int h = 0;
+  CHFSI_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  return h ? 0 : 1;
+}
+
+}  // namespace chfsi
