@@ -53,6 +53,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(python paper_2410_02754_amd/build.py)")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the library binds to the runtime that owns torch's memory and streams
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
     pd = C.POINTER(C.c_double)

@@ -45,6 +45,14 @@ template <class T> struct Vec4;
 template <> struct Vec4<double> { typedef d4 type; };
 template <> struct Vec4<float> { typedef f4 type; };
 
+// Row (within the 16x16 tile) of accumulator element j held by `lane`; the
+// column is lane % 16.  The two 16x16x4 MFMAs distribute rows differently on
+// gfx950: FP32 gives lane/16 groups of four consecutive rows, FP64 interleaves
+// (row = lane/16 + 4 j).  Verified on the device with known operands.
+template <class T> __device__ __forceinline__ int acc_row(int lane, int j);
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int j) { return 4 * (lane >> 4) + j; }
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int j) { return (lane >> 4) + 4 * j; }
+
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 #define LAUNCH_CHECK() CHFSI_HIP(hipGetLastError())
@@ -278,10 +286,10 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
   }
 
   if (!row_active) return;
-  // epilogue: lane holds rows 4*(lane/16)+j, column lane%16 of each 16x16 tile
+  // epilogue: lane holds rows acc_row(lane, j), column lane%16 of each 16x16 tile
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int rl = rb * 16 + 4 * (lane >> 4) + j;
+    const int rl = rb * 16 + acc_row<T>(lane, j);
     if (rl >= nloc) continue;
     const int64_t node = sNode[rl];
     double2* w0 = W + (2 * node) * ldw;
@@ -638,7 +646,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int ri = i0 + a * 16 + 4 * (lane >> 4) + j;
+        const int ri = i0 + a * 16 + acc_row<double>(lane, j);
         const int cj = j0 + b * 16 + (lane & 15);
         if (ri < n && cj < n) out[(size_t)ri * n + cj] = double2{sr[a][b][j], si[a][b][j]};
       }
@@ -741,7 +749,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t r = rbase + a * 16 + 4 * (lane >> 4) + j;
+        const int64_t r = rbase + a * 16 + acc_row<double>(lane, j);
         const int cj = j0 + b * 16 + (lane & 15);
         if (r < prow && cj < n) X[r * ldx + cj] = double2{cr[a][b][j], ci[a][b][j]};
       }
