@@ -62,7 +62,8 @@ def build_operator(s, torch):
 def run_passes(op, s, X, W, Wf, b, theta, n_pass, prec, torch, label):
     """n_pass passes; returns (theta, resid, per-pass seconds, filter seconds, filter stats)."""
     times, ftimes = [], []
-    fstats = {"flops": 0.0, "cell_flops": 0.0, "cell_exec": 0.0, "cell_ms": 0.0, "cell_launches": 0}
+    fstats = {"flops": 0.0, "cell_flops": 0.0, "cell_exec": 0.0, "cell_ms": 0.0, "cell_launches": 0,
+              "stage_ms": {}}
     cell_key = "cell_fp64" if prec == "fp64" else "cell_fp32"
     r = None
     for p in range(n_pass):
@@ -81,10 +82,15 @@ def run_passes(op, s, X, W, Wf, b, theta, n_pass, prec, torch, label):
         fstats["cell_exec"] += st[cell_key]["exec_flops"]
         fstats["cell_ms"] += st[cell_key]["ms"]
         fstats["cell_launches"] += st[cell_key]["launches"]
+        for k, v in st.items():
+            fstats["stage_ms"]["filter_" + k] = fstats["stage_ms"].get("filter_" + k, 0.0) + v["ms"]
+        op.stats_reset()
         op.chol_gs(X)
         theta, r = op.rayleigh_ritz(X, W)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        for k, v in op.stats().items():
+            fstats["stage_ms"]["rr_" + k] = fstats["stage_ms"].get("rr_" + k, 0.0) + v["ms"]
         times.append(t2 - t0)
         ftimes.append(t1 - t0)
         log(f"[bench] {label} pass {p + 1}/{n_pass}: {t2 - t0:.2f} s (filter {t1 - t0:.2f} s), "
@@ -206,6 +212,7 @@ def main():
                      "flops_per_launch": cell_per_launch, "mean_launch_ms": round(cell_ms, 4),
                      "executed_mfma_tflops": round(exec_tf, 3),
                      "executed_frac": round(exec_tf / PEAK_FP64, 4)},
+        "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in fst["stage_ms"].items() if v > 0},
         "setup_s": round(t_setup, 2), "lanczos_s": round(t_lanczos, 3),
         "theta_min": float(theta64[0]), "theta_max": float(theta64[-1]), "max_resid": float(np.max(r64)),
     }
@@ -232,6 +239,7 @@ def main():
             "within_1e-7_Ha": bool(dth.max() <= 1e-7),
             "cell_fp32_achieved_tflops": round(m_ach, 3),
             "cell_fp32_frac_of_157.3": round(m_ach / PEAK_FP32, 4),
+            "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in mst["stage_ms"].items() if v > 0},
         }
         log(f"[bench] mixed: max |dtheta| vs fp64 = {dth.max():.3e} Ha")
     op.close()
