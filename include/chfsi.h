@@ -166,6 +166,40 @@ int chfsi_rayleigh_ritz(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* wo
 int chfsi_lanczos_bounds(chfsi_ctx* ctx, int ik, int steps, const void* v0_d, double* lo,
                          double* hi);
 
+/* ---- Adjoint (gradients of a real loss L through the operator and the filter).
+ * Convention: for a complex block Z the gradient is Zbar = 2 dL/d conj(Z)
+ * (the PyTorch convention), so that dL = Re <Zbar, dZ>, <a,b> = sum conj(a) b.
+ * The operator depends linearly on the fields at the quadrature points
+ * (eqn:FEHlocEl); for blocks L, Y its derivatives pair as
+ *   Re <L, dH_hat/dV(e,q) Y>   = w_q J Re sum_n l_n(q)^H y_n(q),
+ *   Re <L, dH_hat/dB_d(e,q) Y> = w_q J Re sum_n l_n(q)^H sigma_d y_n(q),
+ * where z(q) = sum_i N_i(r_q) (M_D^{-1/2} Z)_i is the unscaled field at r_q.
+ * For L = sum_n Re <x_n|H_hat|x_n> these are w_q J times the density and the
+ * magnetisation of eqn:rho and eqn:mag. */
+
+/* Adjoint of chfsi_apply_H (Y = H_hat X): Xbar_d [2M][ldxb] = H_hat Ybar; ADDS
+ * dL/dV into dV_d [E][nq^3] and dL/dB_d into dB_d [E][nq^3][3] (device, float64;
+ * the caller zeroes them).  FP64.  Requires n_q <= 10. */
+int chfsi_apply_H_backward(chfsi_ctx* ctx, int ik, const void* X_d, int64_t ldx, const void* Ybar_d,
+                           int64_t ldyb, void* Xbar_d, int64_t ldxb, int n_vec, double* dV_d,
+                           double* dB_d);
+
+/* Workspace bytes needed by chfsi_cheb_filter_backward for these sizes. */
+size_t chfsi_filter_backward_workspace(const chfsi_ctx* ctx, int n_vec, int degree, int ckpt_every);
+
+/* Adjoint of chfsi_cheb_filter (same degree and bounds, FP64): with the forward
+ * states Y_0 = X, ..., Y_m and Ybar = 2 dL/d conj(Y_m), runs the reverse
+ * recurrence Lam_m = Ybar, Lam_{k-1} = alpha_k (H_hat - c) Lam_k + beta_{k+1} Lam_{k+1}
+ * (the same operator chain: H_hat is Hermitian and the coefficients real), sets
+ * Xbar_d = Lam_0 and ADDS sum_k alpha_k (dV, dB)(Lam_k, Y_{k-1}) into dV_d, dB_d.
+ * Forward states are recomputed segment by segment from checkpoint pairs
+ * (Y_{jc}, Y_{jc+1}), c = ckpt_every >= 1, kept in work_d (device, caller-owned,
+ * at least chfsi_filter_backward_workspace bytes).  X_d is not modified. */
+int chfsi_cheb_filter_backward(chfsi_ctx* ctx, int ik, const void* X_d, int64_t ldx, const void* Ybar_d,
+                               int64_t ldyb, void* Xbar_d, int64_t ldxb, int n_vec, int degree, double a,
+                               double b, double a0, int ckpt_every, void* work_d, size_t work_bytes,
+                               double* dV_d, double* dB_d);
+
 /* Fill rows [row0, row0+n_rows) x columns [col0, col0+n_vec) of a seeded
  * [..][n_total_cols] multivector into X_d [n_rows][ld]:
  * X[r][n] = u(2j) + i u(2j+1), j = r * n_total_cols + n, u(i) = 2 w - 1 with w

@@ -14,7 +14,8 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_set_atoms", "chfsi_apply_H", "chfsi_cheb_filter", "chfsi_chol_gs",
             "chfsi_rayleigh_ritz", "chfsi_lanczos_bounds", "chfsi_fill_random", "chfsi_sync",
             "chfsi_last_error", "chfsi_version", "chfsi_stats_enable", "chfsi_stats_read",
-            "chfsi_stats_reset"]
+            "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
+            "chfsi_cheb_filter_backward"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -74,6 +75,10 @@ def load():
         "chfsi_lanczos_bounds": ([vp, i32, i32, vp, pd, pd], i32),
         "chfsi_fill_random": ([vp, vp, i64, i32, i64, C.c_uint64, i64, i32, i64], i32),
         "chfsi_sync": ([vp], i32),
+        "chfsi_apply_H_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, vp, vp], i32),
+        "chfsi_filter_backward_workspace": ([vp, i32, i32, i32], C.c_size_t),
+        "chfsi_cheb_filter_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, i32, dbl, dbl, dbl,
+                                        i32, vp, C.c_size_t, vp, vp], i32),
         "chfsi_stats_enable": ([vp, i32], i32),
         "chfsi_stats_read": ([vp, C.POINTER(StageStats)], i32),
         "chfsi_stats_reset": ([vp], i32),

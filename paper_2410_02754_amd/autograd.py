@@ -1,0 +1,76 @@
+"""torch.autograd.Function wrappers of the operator and the Chebyshev filter,
+differentiable in the block X and in the fields V_eff, B_xc at the quadrature
+points.  Forward and backward both run in the library (the backward is the
+hand-written adjoint of chfsi_apply_H / chfsi_cheb_filter)."""
+from __future__ import annotations
+
+import torch
+
+
+def _ensure_fields(op, V, B):
+    key = (V.data_ptr(), V._version, B.data_ptr(), B._version)
+    if getattr(op, "_field_key", None) != key:
+        op.set_local(V.detach().contiguous(), B.detach().contiguous())
+        op._field_key = key
+
+
+class ApplyH(torch.autograd.Function):
+    """Y = H_hat(V, B) X."""
+
+    @staticmethod
+    def forward(ctx, X, V, B, op, ik=0):
+        _ensure_fields(op, V, B)
+        X = X.contiguous()
+        Y = torch.empty_like(X)
+        op.apply_H(X, Y, ik=ik)
+        ctx.save_for_backward(X)
+        ctx.op, ctx.ik = op, ik
+        ctx.shapes = (V.shape, B.shape)
+        return Y
+
+    @staticmethod
+    def backward(ctx, Ybar):
+        (X,) = ctx.saved_tensors
+        op = ctx.op
+        Xbar = torch.empty_like(X)
+        dV = torch.zeros(ctx.shapes[0], dtype=torch.float64, device=X.device)
+        dB = torch.zeros(ctx.shapes[1], dtype=torch.float64, device=X.device)
+        op.apply_H_backward(X, Ybar.contiguous(), Xbar, dV, dB, ik=ctx.ik)
+        return Xbar, dV, dB, None, None
+
+
+class ChebFilter(torch.autograd.Function):
+    """Y = p_m(H_hat(V, B)) X, the scaled degree-m Chebyshev filter with bounds (a, b, a0).
+    Backward recomputes forward states from checkpoint pairs every `ckpt_every` steps."""
+
+    @staticmethod
+    def forward(ctx, X, V, B, op, degree, a, b, a0, ckpt_every=4, ik=0):
+        _ensure_fields(op, V, B)
+        X = X.contiguous()
+        Y = X.clone()
+        work = torch.empty_like(X)
+        op.cheb_filter(Y, work, degree, a, b, a0, ik=ik)
+        ctx.save_for_backward(X)
+        ctx.op, ctx.ik = op, ik
+        ctx.args = (degree, a, b, a0, ckpt_every)
+        ctx.shapes = (V.shape, B.shape)
+        return Y
+
+    @staticmethod
+    def backward(ctx, Ybar):
+        (X,) = ctx.saved_tensors
+        degree, a, b, a0, ck = ctx.args
+        Xbar = torch.empty_like(X)
+        dV = torch.zeros(ctx.shapes[0], dtype=torch.float64, device=X.device)
+        dB = torch.zeros(ctx.shapes[1], dtype=torch.float64, device=X.device)
+        ctx.op.cheb_filter_backward(X, Ybar.contiguous(), Xbar, dV, dB, degree, a, b, a0, ckpt_every=ck,
+                                    ik=ctx.ik)
+        return Xbar, dV, dB, None, None, None, None, None, None, None
+
+
+def apply_h(X, V, B, op, ik=0):
+    return ApplyH.apply(X, V, B, op, ik)
+
+
+def cheb_filter(X, V, B, op, degree, a, b, a0, ckpt_every=4, ik=0):
+    return ChebFilter.apply(X, V, B, op, degree, a, b, a0, ckpt_every, ik)

@@ -172,6 +172,47 @@ class Operator:
                                              C.c_uint64(seed), row0, col0, ntc))
         return X
 
+    # ---------------------------------------------------------------- adjoint
+    def _fields_grad(self, dV, dB):
+        torch = _torch()
+        for t, shp in ((dV, (self.n_cells, self.nq3)), (dB, (self.n_cells, self.nq3, 3))):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shp:
+                raise ValueError(f"gradient buffers must be contiguous float64 CUDA tensors {shp}")
+
+    def apply_H_backward(self, X, Ybar, Xbar, dV, dB, ik: int = 0):
+        """Xbar = H_hat Ybar; dV, dB += dL/dV, dL/dB (Ybar = 2 dL/d conj(Y))."""
+        px, ldx, n = _block(X, "X")
+        pg, ldg, ng = _block(Ybar, "Ybar")
+        pb, ldb, nb = _block(Xbar, "Xbar")
+        if not (n == ng == nb):
+            raise ValueError("X, Ybar, Xbar must have the same width")
+        self._fields_grad(dV, dB)
+        self._chk(self.lib.chfsi_apply_H_backward(self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(pg), ldg,
+                                                  C.c_void_p(pb), ldb, n, C.c_void_p(dV.data_ptr()),
+                                                  C.c_void_p(dB.data_ptr())))
+        return Xbar
+
+    def filter_backward_workspace(self, n_vec: int, degree: int, ckpt_every: int) -> int:
+        return int(self.lib.chfsi_filter_backward_workspace(self.ctx, n_vec, degree, ckpt_every))
+
+    def cheb_filter_backward(self, X, Ybar, Xbar, dV, dB, degree, a, b, a0, ckpt_every: int = 4,
+                             ik: int = 0, work=None):
+        torch = _torch()
+        px, ldx, n = _block(X, "X")
+        pg, ldg, ng = _block(Ybar, "Ybar")
+        pb, ldb, nb = _block(Xbar, "Xbar")
+        if not (n == ng == nb):
+            raise ValueError("X, Ybar, Xbar must have the same width")
+        self._fields_grad(dV, dB)
+        need = self.filter_backward_workspace(n, degree, ckpt_every)
+        if work is None or work.numel() * work.element_size() < need:
+            work = torch.empty(need // 16 + 1, dtype=torch.complex128, device=X.device)
+        self._chk(self.lib.chfsi_cheb_filter_backward(
+            self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(pg), ldg, C.c_void_p(pb), ldb, n, int(degree),
+            float(a), float(b), float(a0), int(ckpt_every), C.c_void_p(work.data_ptr()),
+            work.numel() * work.element_size(), C.c_void_p(dV.data_ptr()), C.c_void_p(dB.data_ptr())))
+        return Xbar
+
     def stats_enable(self, on: bool = True):
         self._chk(self.lib.chfsi_stats_enable(self.ctx, 1 if on else 0))
 

@@ -354,6 +354,100 @@ int chfsi_lanczos_bounds(chfsi_ctx* c, int ik, int steps, const void* v0, double
   API_END(c)
 }
 
+int chfsi_apply_H_backward(chfsi_ctx* c, int ik, const void* X, int64_t ldx, const void* Ybar, int64_t ldyb,
+                           void* Xbar, int64_t ldxb, int n_vec, double* dV, double* dB) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, Ybar, ldyb, n_vec, "Ybar");
+  check_block(c, Xbar, ldxb, n_vec, "Xbar");
+  CHFSI_CHECK(dV && dB, CHFSI_EINVAL, "dV_d and dB_d must be non-NULL");
+  CHFSI_CHECK(Xbar != Ybar && Xbar != X, CHFSI_EINVAL, "Xbar must not alias X or Ybar");
+  KPoint& kp = kpoint(c, ik);
+  apply_H(c, kp, (const double2*)Ybar, ldyb, (double2*)Xbar, ldxb, n_vec, CHFSI_PREC_FP64, 1.0, 0.0, 0.0);
+  cross_density(c, (const double2*)Ybar, ldyb, (const double2*)X, ldx, n_vec, 1.0, dV, dB);
+  API_END(c)
+}
+
+static int filter_n_segments(int degree, int ck) { return (degree + ck - 1) / ck; }
+
+size_t chfsi_filter_backward_workspace(const chfsi_ctx* c, int n_vec, int degree, int ck) {
+  if (!c || n_vec < 1 || degree < 1 || ck < 1) return 0;
+  const size_t blk = (size_t)2 * c->n_nodes * n_vec * sizeof(double2);
+  return blk * (2 * (size_t)filter_n_segments(degree, ck) + std::max(ck, 3) + 2);
+}
+
+int chfsi_cheb_filter_backward(chfsi_ctx* c, int ik, const void* X, int64_t ldx, const void* Ybar, int64_t ldyb,
+                               void* Xbar, int64_t ldxb, int n_vec, int degree, double a, double b, double a0,
+                               int ck, void* work, size_t work_bytes, double* dV, double* dB) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, Ybar, ldyb, n_vec, "Ybar");
+  check_block(c, Xbar, ldxb, n_vec, "Xbar");
+  CHFSI_CHECK(dV && dB && work, CHFSI_EINVAL, "dV_d, dB_d and work_d must be non-NULL");
+  CHFSI_CHECK(degree >= 1 && ck >= 1, CHFSI_EINVAL, "degree and ckpt_every must be >= 1");
+  CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
+              "filter bounds must satisfy a0 < a < b");
+  CHFSI_CHECK(work_bytes >= chfsi_filter_backward_workspace(c, n_vec, degree, ck), CHFSI_EINVAL,
+              "workspace too small");
+  KPoint& kp = kpoint(c, ik);
+  const int m = degree;
+  const int64_t rows = 2 * c->n_nodes;
+  const size_t blk = (size_t)rows * n_vec;
+  const int J = filter_n_segments(m, ck);
+  const int nseg = std::max(ck, 3);
+  double2* base = (double2*)work;
+  auto ckp = [&](int j, int which) { return base + (2 * (size_t)j + which) * blk; };
+  auto seg = [&](int i) { return base + (2 * (size_t)J + i) * blk; };
+  double2* lam[2] = {base + (2 * (size_t)J + nseg) * blk, base + (2 * (size_t)J + nseg + 1) * blk};
+  // recurrence coefficients: Y_k = al_k (H - c) Y_{k-1} + be_k Y_{k-2}, k = 1..m
+  const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
+  const double s1 = e / (a0 - cc);
+  std::vector<double> al(m + 2, 0.0), be(m + 2, 0.0);
+  double sg = s1;
+  al[1] = s1 / e;
+  for (int k = 2; k <= m; ++k) {
+    const double sn = 1.0 / (2.0 / s1 - sg);
+    al[k] = 2.0 * sn / e;
+    be[k] = -sg * sn;
+    sg = sn;
+  }
+  // state k lives in checkpoint j = k / ck (slot 0 or 1) or in seg[k % ck]
+  auto slot = [&](int k) -> double2* {
+    const int j = k / ck, i = k % ck;
+    return i < 2 ? ckp(j, i) : seg(i);
+  };
+  auto step = [&](int k) {            // computes state k (2 <= k) from k-1, k-2 into its slot
+    apply_H2(c, kp, slot(k - 1), n_vec, slot(k), n_vec, slot(k - 2), n_vec, n_vec, CHFSI_PREC_FP64, al[k],
+             be[k], -cc * al[k]);
+  };
+  // forward: checkpoint pairs (Y_{jc}, Y_{jc+1}) for states 0 .. m-1
+  launch_copy_rows(c, slot(0), n_vec, (const double2*)X, ldx, rows, n_vec);
+  if (m >= 2)
+    apply_H(c, kp, slot(0), n_vec, slot(1), n_vec, n_vec, CHFSI_PREC_FP64, al[1], 0.0, -cc * al[1]);
+  for (int k = 2; k <= m - 1; ++k) step(k);
+  // backward
+  launch_copy_rows(c, lam[0], n_vec, (const double2*)Ybar, ldyb, rows, n_vec);
+  int cur = 0;                        // lam[cur] = Lam_k, lam[cur ^ 1] = Lam_{k+1}
+  for (int j = J - 1; j >= 0; --j) {
+    const int k_lo = j * ck;          // states k_lo .. k_hi-1 are needed as Y_{k-1}
+    const int k_hi = std::min(k_lo + ck, m);
+    for (int k = k_lo + 2; k <= k_hi - 1; ++k) step(k);   // recompute this segment
+    for (int k = k_hi; k >= k_lo + 1; --k) {
+      cross_density(c, lam[cur], n_vec, slot(k - 1), n_vec, n_vec, al[k], dV, dB);
+      const double bn = (k < m) ? be[k + 1] : 0.0;
+      apply_H(c, kp, lam[cur], n_vec, lam[cur ^ 1], n_vec, n_vec, CHFSI_PREC_FP64, al[k], bn, -cc * al[k]);
+      cur ^= 1;
+    }
+  }
+  launch_copy_rows(c, (double2*)Xbar, ldxb, lam[cur], n_vec, rows, n_vec);
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  API_END(c)
+}
+
 int chfsi_fill_random(chfsi_ctx* c, void* X, int64_t n_rows, int n_vec, int64_t ld, uint64_t seed, int64_t row0,
                       int col0, int64_t ntc) {
   if (!c) return CHFSI_EINVAL;

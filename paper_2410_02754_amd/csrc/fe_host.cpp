@@ -492,7 +492,6 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
   nl.n_entries = 0;
   nl.max_pj = 1;
   nl.n_chunks = 0;
-  nl.n_unodes = 0;
   if (n_atoms == 0) return;
   std::vector<AtomWork> work(n_atoms);
   parallel_for(n_atoms, [&](int a) { atom_tables(c, kp.k, atoms[a], work[a]); });
@@ -546,17 +545,13 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
   for (int a = 0; a < n_atoms; ++a)
     for (int s = atom_off[a]; s < atom_off[a + 1]; ++s) trip[s] = {sup[s], a, s};
   std::sort(trip.begin(), trip.end());
-  std::vector<int32_t> unode, uoff, ulist_e, ulist_a;
+  std::vector<int32_t> noff(c->n_nodes + 1, 0), nl_e(trip.size()), nl_a(trip.size());
   for (size_t i = 0; i < trip.size(); ++i) {
-    if (i == 0 || trip[i][0] != trip[i - 1][0]) {
-      unode.push_back(trip[i][0]);
-      uoff.push_back((int32_t)i);
-    }
-    ulist_a.push_back(trip[i][1]);
-    ulist_e.push_back(trip[i][2]);
+    noff[trip[i][0] + 1] += 1;
+    nl_a[i] = trip[i][1];
+    nl_e[i] = trip[i][2];
   }
-  uoff.push_back((int32_t)trip.size());
-  nl.n_unodes = (int64_t)unode.size();
+  for (int64_t i = 0; i < c->n_nodes; ++i) noff[i + 1] += noff[i];
   hipStream_t s = c->stream;
   nl.sup_node.upload(sup.data(), sup.size(), s);
   nl.proj.upload(proj.data(), proj.size(), s);
@@ -568,10 +563,9 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
   nl.chunk_begin.upload(ch_b.data(), ch_b.size(), s);
   nl.chunk_end.upload(ch_e.data(), ch_e.size(), s);
   nl.atom_chunk0.upload(atom_chunk0.data(), atom_chunk0.size(), s);
-  nl.unode.upload(unode.data(), unode.size(), s);
-  nl.unode_off.upload(uoff.data(), uoff.size(), s);
-  nl.ulist_entry.upload(ulist_e.data(), ulist_e.size(), s);
-  nl.ulist_atom.upload(ulist_a.data(), ulist_a.size(), s);
+  nl.node_off.upload(noff.data(), noff.size(), s);
+  nl.nlist_entry.upload(nl_e.data(), nl_e.size(), s);
+  nl.nlist_atom.upload(nl_a.data(), nl_a.size(), s);
   CHFSI_HIP(hipStreamSynchronize(s));   // host vectors go out of scope
 }
 

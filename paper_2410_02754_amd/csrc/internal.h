@@ -107,12 +107,11 @@ struct NonlocalK {
   DevBuf<int32_t> chunk_begin;  // [n_chunks]
   DevBuf<int32_t> chunk_end;    // [n_chunks]
   DevBuf<int32_t> atom_chunk0;  // [n_atoms + 1]
-  // node-centric back-product: unique nodes, each with its (entry, atom) list
-  int64_t n_unodes = 0;
-  DevBuf<int32_t> unode;        // [n_unodes] global node
-  DevBuf<int32_t> unode_off;    // [n_unodes + 1] into ulist
-  DevBuf<int32_t> ulist_entry;  // [n_entries] entry index
-  DevBuf<int32_t> ulist_atom;   // [n_entries]
+  // node-centric back-product over every global node: the (entry, atom) pairs
+  // of node I are nlist_*[node_off[I] .. node_off[I+1])
+  DevBuf<int32_t> node_off;     // [n_nodes + 1]
+  DevBuf<int32_t> nlist_entry;  // [n_entries]
+  DevBuf<int32_t> nlist_atom;   // [n_entries]
 };
 constexpr int kNlChunk = 256;
 
@@ -205,6 +204,13 @@ int check_finite(chfsi_ctx* c, const double* p, int64_t n);
 // W <- alpha H_hat X + beta W + gamma X   (W is not read when beta == 0)
 void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
              int n_vec, int prec, double alpha, double beta, double gamma);
+// W <- alpha H_hat X + beta Wold + gamma X   (Wold may equal W; not read when beta == 0)
+void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+              const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta,
+              double gamma);
+// dV[e][q] += alpha w_q J Re sum_n l^H y, dB_d[e][q] += alpha w_q J Re sum_n l^H sigma_d y
+void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
+                   double alpha, double* dV, double* dB);
 void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,
                        int64_t rows, int n_vec, double beta, double gamma);
 void launch_copy_rows(chfsi_ctx* c, double2* dst, int64_t ldd, const double2* src, int64_t lds,

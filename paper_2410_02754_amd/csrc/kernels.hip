@@ -170,17 +170,25 @@ template <class T, int CB, bool HAS_S>
 __global__ __launch_bounds__(256) void cell_apply_kernel(
     const T* __restrict__ cm, const int32_t* __restrict__ cell_nodes,
     const int32_t* __restrict__ cells, int nloc, int nrb, int nkb, int nmat, int n_rowtiles,
-    int n_coltiles, const double2* __restrict__ X, int64_t ldx, double2* __restrict__ W, int64_t ldw,
-    int n_vec, double alpha) {
+    int n_coltiles, int n_work, const double2* __restrict__ X, int64_t ldx, double2* __restrict__ W,
+    int64_t ldw, int n_vec, double alpha) {
   typedef typename Vec4<T>::type V4;
   constexpr int BN = 32 * CB;
   constexpr int BK = 8;
+  constexpr int PAD = 16;                 // row pad: 4 k-rows of a fragment hit disjoint banks
   constexpr int NPRE = (BK * 2 * BN) / 256;
-  __shared__ T sB[2][4][BK][BN];
+  constexpr int NM = HAS_S ? 5 : 4;
+  __shared__ T sB[2][4][BK][BN + PAD];
   __shared__ int32_t sNode[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
 
+  // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+  // XCD gets a contiguous range of (cell, row tile, column tile) work and the
+  // row tiles of one cell share that XCD's L2 for the gathered rows.
+  const int per_xcd = (n_work + 7) / 8;
+  const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (bid >= n_work) return;              // uniform over the block, before any barrier
+
   const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
   const int ct = bid % n_coltiles;
   const int rt = (bid / n_coltiles) % n_rowtiles;
   const int ci = bid / (n_coltiles * n_rowtiles);
@@ -203,6 +211,7 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
   const T* Abase = cm + ((size_t)(e * nrb + (row_active ? rb : 0)) * nkb) * nmat * 64 + lane;
   const int nstage = nkb / 2;
   double2 pre[NPRE];
+  T aC[2][NM], aN[2][NM];
 
   auto gload = [&](int s) {
 #pragma unroll
@@ -225,19 +234,30 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
       sB[buf][2 * sp + 1][kk][col] = (T)pre[j].y;
     }
   };
+  auto aload = [&](int s, T (&dst)[2][NM]) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const T* Ap = Abase + (size_t)(s * 2 + kk) * nmat * 64;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) dst[kk][m] = Ap[m * 64];
+    }
+  };
 
+  if (row_active) aload(0, aC);
   gload(0);
   lstore(0);
   __syncthreads();
   for (int s = 0; s < nstage; ++s) {
     const int buf = s & 1;
-    if (s + 1 < nstage) gload(s + 1);
+    if (s + 1 < nstage) {
+      gload(s + 1);
+      if (row_active) aload(s + 1, aN);
+    }
     if (row_active) {
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
-        const T* Ap = Abase + (size_t)(s * 2 + kk) * nmat * 64;
-        const T hp = Ap[0], hm = Ap[64], bx = Ap[128], by = Ap[192];
-        const T sv = HAS_S ? Ap[256] : (T)0;
+        const T hp = aC[kk][0], hm = aC[kk][1], bx = aC[kk][2], by = aC[kk][3];
+        const T sv = HAS_S ? aC[kk][NM - 1] : (T)0;
         const T nby = -by, nsv = -sv;
         const int krow = kk * 4 + (lane >> 4);
         T ba[CB], bb[CB], bc[CB], bd[CB];
@@ -283,6 +303,10 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
     }
     if (s + 1 < nstage) lstore(buf ^ 1);
     __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) aC[kk][m] = aN[kk][m];
   }
 
   if (!row_active) return;
@@ -327,9 +351,10 @@ static void launch_cells(chfsi_ctx* c, const T* cm, int nmat, const double2* X, 
     const double bytes = (double)n_in * ((double)nmat * c->nloc * c->nloc * sizeof(T) +
                                          3.0 * c->nloc * 2.0 * n_vec * sizeof(double2));
     StageTimer tm(c, sizeof(T) == 8 ? CHFSI_STAGE_CELL_FP64 : CHFSI_STAGE_CELL_FP32, flops, exec, bytes);
-    hipLaunchKernelGGL((cell_apply_kernel<T, CB, HAS_S>), dim3(nblk), dim3(256), 0, c->stream, cm,
+    const int grid = 8 * ((nblk + 7) / 8);
+    hipLaunchKernelGGL((cell_apply_kernel<T, CB, HAS_S>), dim3(grid), dim3(256), 0, c->stream, cm,
                        c->cell_nodes.ptr, c->colour_cells.ptr + c->colour_off[k], c->nloc, c->nrb,
-                       c->nkb, nmat, n_rowtiles, n_coltiles, X, ldx, W, ldw, n_vec, alpha);
+                       c->nkb, nmat, n_rowtiles, n_coltiles, nblk, X, ldx, W, ldw, n_vec, alpha);
     LAUNCH_CHECK();
   }
 }
@@ -410,60 +435,117 @@ template <> struct C2<float> { typedef float2 type; };
 
 constexpr int kMaxPj = 9;
 
-// Partial C[2 chi + s][n] over one chunk of an atom's support nodes:
-// sum_j conj(P[j][chi]) X[2 node_j + s][n].  Block: 64 columns x 2 spins.
+// Contraction partials, one wave per (chunk of an atom's support, 64-column
+// tile): partial[chunk][2 chi + s][n] = sum_j conj(P[j][chi]) X[2 node_j + s][n].
+// Entries are processed four at a time so that eight independent row loads
+// are in flight per wave; the projector values are wave-uniform (scalar loads).
 template <class T>
-__global__ __launch_bounds__(128) void nl_project_kernel(
+__global__ __launch_bounds__(256) void nl_contract_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ sup_node,
     const int32_t* __restrict__ chunk_atom, const int32_t* __restrict__ chunk_begin,
     const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ atom_npj, int max_pj,
-    const double2* __restrict__ X, int64_t ldx, int n_vec, typename C2<T>::type* __restrict__ partial) {
+    int n_work, int n_coltiles, const double2* __restrict__ X, int64_t ldx, int n_vec,
+    typename C2<T>::type* __restrict__ partial) {
   typedef typename C2<T>::type CT;
-  __shared__ CT sP[kNlChunk * kMaxPj];
-  __shared__ int32_t sN[kNlChunk];
-  const int ch = blockIdx.x;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (wid >= n_work) return;
+  const int lane = threadIdx.x & 63;
+  const int ch = wid / n_coltiles, ct = wid - ch * n_coltiles;
   const int a = chunk_atom[ch], b = chunk_begin[ch], e = chunk_end[ch];
   const int npj = atom_npj[a];
-  const int cnt = e - b;
-  for (int t = threadIdx.x; t < cnt * max_pj; t += blockDim.x) sP[t] = proj[(size_t)b * max_pj + t];
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) sN[t] = sup_node[b + t];
-  __syncthreads();
-  const int col = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int sp = threadIdx.x >> 6;
-  T ar[kMaxPj], ai[kMaxPj];
+  const int col = ct * 64 + lane;
+  const bool cv = col < n_vec;
+  T ar[2][kMaxPj], ai[2][kMaxPj];
 #pragma unroll
-  for (int x = 0; x < kMaxPj; ++x) ar[x] = ai[x] = (T)0;
-  if (col < n_vec) {
-    for (int j = 0; j < cnt; ++j) {
-      const double2 xv = X[(2 * (int64_t)sN[j] + sp) * ldx + col];
-      const T xr = (T)xv.x, xi = (T)xv.y;
+  for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-      for (int x = 0; x < kMaxPj; ++x) {
-        if (x < npj) {
-          const CT p = sP[j * max_pj + x];
-          ar[x] += p.x * xr + p.y * xi;     // conj(p) * x
-          ai[x] += p.x * xi - p.y * xr;
+    for (int x = 0; x < kMaxPj; ++x) ar[sp][x] = ai[sp][x] = (T)0;
+  auto accum = [&](int j, const double2& x0, const double2& x1) {
+    const T xr[2] = {(T)x0.x, (T)x1.x}, xi[2] = {(T)x0.y, (T)x1.y};
+#pragma unroll
+    for (int x = 0; x < kMaxPj; ++x) {
+      if (x < npj) {
+        const CT p = proj[(size_t)j * max_pj + x];
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+          ar[sp][x] += p.x * xr[sp] + p.y * xi[sp];     // conj(p) * x
+          ai[sp][x] += p.x * xi[sp] - p.y * xr[sp];
         }
       }
     }
+  };
+  int j = b;
+  for (; j + 3 < e; j += 4) {
+    double2 x[4][2];
 #pragma unroll
-    for (int x = 0; x < kMaxPj; ++x) {
-      if (x < max_pj) {
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = 2 * (int64_t)sup_node[j + u];
+      x[u][0] = cv ? X[r * ldx + col] : double2{0.0, 0.0};
+      x[u][1] = cv ? X[(r + 1) * ldx + col] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) accum(j + u, x[u][0], x[u][1]);
+  }
+  for (; j < e; ++j) {
+    const int64_t r = 2 * (int64_t)sup_node[j];
+    const double2 x0 = cv ? X[r * ldx + col] : double2{0.0, 0.0};
+    const double2 x1 = cv ? X[(r + 1) * ldx + col] : double2{0.0, 0.0};
+    accum(j, x0, x1);
+  }
+  if (!cv) return;
+#pragma unroll
+  for (int x = 0; x < kMaxPj; ++x)
+    if (x < max_pj)
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
         CT v;
-        v.x = ar[x];
-        v.y = ai[x];
+        v.x = ar[sp][x];
+        v.y = ai[sp][x];
         partial[((size_t)ch * 2 * max_pj + 2 * x + sp) * n_vec + col] = v;
       }
-    }
-  }
 }
 
-// C'[a][r][n] = alpha sum_r' Delta_a[r][r'] sum_{chunks of a} partial[chunk][r'][n]
+// Csum[a][r][n] = sum over the chunks of atom a of partial[chunk][r][n] (chunk order fixed)
 template <class T>
-__global__ __launch_bounds__(64) void nl_couple_kernel(
-    const typename C2<T>::type* __restrict__ partial, const int32_t* __restrict__ atom_chunk0,
-    const int32_t* __restrict__ atom_npj, const double2* __restrict__ delta, int max_pj, int n_vec,
-    double alpha, typename C2<T>::type* __restrict__ Cp) {
+__global__ __launch_bounds__(64) void nl_reduce_kernel(const typename C2<T>::type* __restrict__ partial,
+                                                       const int32_t* __restrict__ atom_chunk0,
+                                                       const int32_t* __restrict__ atom_npj, int max_pj,
+                                                       int n_vec, typename C2<T>::type* __restrict__ Csum) {
+  typedef typename C2<T>::type CT;
+  const int a = blockIdx.x, r = blockIdx.y;
+  const int col = blockIdx.z * 64 + threadIdx.x;
+  const int mr = 2 * max_pj;
+  if (r >= 2 * atom_npj[a] || col >= n_vec) return;
+  T sr = 0, si = 0;
+  const int c0 = atom_chunk0[a], c1 = atom_chunk0[a + 1];
+  int ch = c0;
+  for (; ch + 3 < c1; ch += 4) {
+    CT v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = partial[((size_t)(ch + u) * mr + r) * n_vec + col];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sr += v[u].x;
+      si += v[u].y;
+    }
+  }
+  for (; ch < c1; ++ch) {
+    const CT v = partial[((size_t)ch * mr + r) * n_vec + col];
+    sr += v.x;
+    si += v.y;
+  }
+  CT o;
+  o.x = sr;
+  o.y = si;
+  Csum[((size_t)a * mr + r) * n_vec + col] = o;
+}
+
+// C'[a][r][n] = alpha sum_r' Delta_a[r][r'] Csum[a][r'][n]
+template <class T>
+__global__ __launch_bounds__(64) void nl_delta_kernel(const typename C2<T>::type* __restrict__ Csum,
+                                                      const int32_t* __restrict__ atom_npj,
+                                                      const double2* __restrict__ delta, int max_pj, int n_vec,
+                                                      double alpha, typename C2<T>::type* __restrict__ Cp) {
   typedef typename C2<T>::type CT;
   const int a = blockIdx.x;
   const int col = blockIdx.y * 64 + threadIdx.x;
@@ -472,26 +554,23 @@ __global__ __launch_bounds__(64) void nl_couple_kernel(
   const int mr = 2 * max_pj;
   T cr[2 * kMaxPj], cim[2 * kMaxPj];
 #pragma unroll
-  for (int r = 0; r < 2 * kMaxPj; ++r) cr[r] = cim[r] = (T)0;
-  for (int ch = atom_chunk0[a]; ch < atom_chunk0[a + 1]; ++ch)
-#pragma unroll
-    for (int r = 0; r < 2 * kMaxPj; ++r)
-      if (r < nr) {
-        const CT v = partial[((size_t)ch * mr + r) * n_vec + col];
-        cr[r] += v.x;
-        cim[r] += v.y;
-      }
-  for (int r = 0; r < mr; ++r) {
-    T sr = 0, si = 0;
-    if (r < nr) {
-#pragma unroll
-      for (int q = 0; q < 2 * kMaxPj; ++q)
-        if (q < nr) {
-          const double2 d = delta[((size_t)a * mr + r) * mr + q];
-          sr += (T)d.x * cr[q] - (T)d.y * cim[q];
-          si += (T)d.x * cim[q] + (T)d.y * cr[q];
-        }
+  for (int q = 0; q < 2 * kMaxPj; ++q) {
+    cr[q] = cim[q] = (T)0;
+    if (q < nr) {
+      const CT v = Csum[((size_t)a * mr + q) * n_vec + col];
+      cr[q] = v.x;
+      cim[q] = v.y;
     }
+  }
+  for (int r = 0; r < nr; ++r) {
+    T sr = 0, si = 0;
+#pragma unroll
+    for (int q = 0; q < 2 * kMaxPj; ++q)
+      if (q < nr) {
+        const double2 d = delta[((size_t)a * mr + r) * mr + q];
+        sr += (T)d.x * cr[q] - (T)d.y * cim[q];
+        si += (T)d.x * cim[q] + (T)d.y * cr[q];
+      }
     CT o;
     o.x = (T)alpha * sr;
     o.y = (T)alpha * si;
@@ -499,100 +578,312 @@ __global__ __launch_bounds__(64) void nl_couple_kernel(
   }
 }
 
-// W[2 node + s][n] += sum_{(entry, atom) at node} sum_chi P[entry][chi] C'[atom][2 chi + s][n];
-// one wave per node, deterministic order of the (entry, atom) list.
+// Recurrence initialisation fused with the nonlocal back-product, one wave per
+// (node, 128-column tile), two columns per lane:
+//   W[2I+s][n] = beta W[2I+s][n] + gamma X[2I+s][n]
+//               + sum_{(entry, atom) at I} sum_chi P[entry][chi] C'[atom][2 chi + s][n]
+// (W is not read when beta == 0; the list is empty for nodes outside every support.)
 template <class T>
-__global__ __launch_bounds__(256) void nl_scatter_kernel(
-    const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ unode,
-    const int32_t* __restrict__ unode_off, const int32_t* __restrict__ ulist_entry,
-    const int32_t* __restrict__ ulist_atom, const int32_t* __restrict__ atom_npj, int max_pj,
-    int64_t n_unodes, const typename C2<T>::type* __restrict__ Cp, int n_vec, double2* __restrict__ W,
-    int64_t ldw) {
+__global__ __launch_bounds__(256) void init_nl_kernel(
+    const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ node_off,
+    const int32_t* __restrict__ nlist_entry, const int32_t* __restrict__ nlist_atom,
+    const int32_t* __restrict__ atom_npj, int max_pj, const typename C2<T>::type* __restrict__ Cp,
+    int has_nl, const double2* __restrict__ X, int64_t ldx, double2* W, int64_t ldw,
+    const double2* Wold, int64_t ldo, int64_t n_nodes, int n_vec, double beta, double gamma) {
   typedef typename C2<T>::type CT;
-  const int64_t un = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t node = __builtin_amdgcn_readfirstlane((int)wid);
+  if (node >= n_nodes) return;
   const int lane = threadIdx.x & 63;
-  if (un >= n_unodes) return;
-  const int64_t node = unode[un];
-  const int l0 = unode_off[un], l1 = unode_off[un + 1];
-  const int mr = 2 * max_pj;
-  for (int col = lane; col < n_vec; col += 64) {
-    T r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+  const int c0 = blockIdx.y * 128 + lane;
+  double2 w[2][2];          // [column half][spin]
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = c0 + 64 * h;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      double2 v = {0.0, 0.0};
+      if (col < n_vec) {
+        const int64_t r = 2 * node + sp;
+        if (beta != 0.0) {
+          const double2 o = Wold[r * ldo + col];
+          v.x = beta * o.x;
+          v.y = beta * o.y;
+        }
+        if (gamma != 0.0) {
+          const double2 xv = X[r * ldx + col];
+          v.x += gamma * xv.x;
+          v.y += gamma * xv.y;
+        }
+      }
+      w[h][sp] = v;
+    }
+  }
+  if (has_nl) {
+    const int l0 = node_off[node], l1 = node_off[node + 1];
+    const int mr = 2 * max_pj;
+    T acc[2][2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) acc[h][sp][0] = acc[h][sp][1] = (T)0;
     for (int t = l0; t < l1; ++t) {
-      const int ent = ulist_entry[t], a = ulist_atom[t];
+      const int ent = nlist_entry[t], a = nlist_atom[t];
       const int npj = atom_npj[a];
       for (int x = 0; x < npj; ++x) {
         const CT p = proj[(size_t)ent * max_pj + x];
-        const CT c0 = Cp[((size_t)a * mr + 2 * x) * n_vec + col];
-        const CT c1 = Cp[((size_t)a * mr + 2 * x + 1) * n_vec + col];
-        r0 += p.x * c0.x - p.y * c0.y;
-        i0 += p.x * c0.y + p.y * c0.x;
-        r1 += p.x * c1.x - p.y * c1.y;
-        i1 += p.x * c1.y + p.y * c1.x;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int col = c0 + 64 * h;
+          if (col >= n_vec) continue;
+#pragma unroll
+          for (int sp = 0; sp < 2; ++sp) {
+            const CT cv = Cp[((size_t)a * mr + 2 * x + sp) * n_vec + col];
+            acc[h][sp][0] += p.x * cv.x - p.y * cv.y;
+            acc[h][sp][1] += p.x * cv.y + p.y * cv.x;
+          }
+        }
       }
     }
-    double2* w0 = W + (2 * node) * ldw + col;
-    double2* w1 = W + (2 * node + 1) * ldw + col;
-    double2 o0 = *w0, o1 = *w1;
-    o0.x += (double)r0;
-    o0.y += (double)i0;
-    o1.x += (double)r1;
-    o1.y += (double)i1;
-    *w0 = o0;
-    *w1 = o1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        w[h][sp].x += (double)acc[h][sp][0];
+        w[h][sp].y += (double)acc[h][sp][1];
+      }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = c0 + 64 * h;
+    if (col < n_vec) {
+      W[(2 * node) * ldw + col] = w[h][0];
+      W[(2 * node + 1) * ldw + col] = w[h][1];
+    }
   }
 }
 
+// Nonlocal coefficients C' = alpha Delta P^H X for every atom; returns the
+// device array [n_atoms][2 max_pj][n_vec] (in the scratch buffer), or null.
 template <class T>
-static void nonlocal_apply(chfsi_ctx* c, NonlocalK& nl, const typename C2<T>::type* proj,
-                           const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
-                           double alpha) {
+static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
+                                                   const typename C2<T>::type* proj, const double2* X,
+                                                   int64_t ldx, int n_vec, double alpha) {
   typedef typename C2<T>::type CT;
-  if (nl.n_atoms == 0 || nl.n_entries == 0) return;
+  if (nl.n_atoms == 0 || nl.n_entries == 0) return nullptr;
   const int mr = 2 * nl.max_pj;
   const size_t n_part = (size_t)nl.n_chunks * mr * n_vec;
   const size_t n_cp = (size_t)nl.n_atoms * mr * n_vec;
-  const size_t bytes = (n_part + n_cp) * sizeof(CT);
+  const size_t bytes = (n_part + 2 * n_cp) * sizeof(CT);
   c->scratch.alloc((bytes + sizeof(double) - 1) / sizeof(double));
   CT* partial = reinterpret_cast<CT*>(c->scratch.ptr);
-  CT* Cp = partial + n_part;
-  const int nct = cdiv(n_vec, 64);
+  CT* Csum = partial + n_part;
+  CT* Cp = Csum + n_cp;
   double nl_flops = 0.0;
   for (const auto& at : nl.atoms)
     nl_flops += 2.0 * 8.0 * at.n_sup * at.n_pj * 2.0 * n_vec + 8.0 * 4.0 * at.n_pj * at.n_pj * n_vec;
-  const double nl_bytes = (double)nl.n_entries * (2.0 * n_vec * sizeof(double2) + nl.max_pj * sizeof(CT)) +
-                          (double)nl.n_unodes * 2.0 * 2.0 * n_vec * sizeof(double2);
+  const double nl_bytes = (double)nl.n_entries * (2.0 * n_vec * sizeof(double2) + nl.max_pj * sizeof(CT));
   StageTimer tm(c, CHFSI_STAGE_NONLOCAL, nl_flops, nl_flops, nl_bytes);
-  hipLaunchKernelGGL(nl_project_kernel<T>, dim3(nl.n_chunks, nct), dim3(128), 0, c->stream, proj,
+  const int nct = cdiv(n_vec, 64);
+  const int n_work = nl.n_chunks * nct;
+  hipLaunchKernelGGL(nl_contract_kernel<T>, dim3(cdiv(n_work, 4)), dim3(256), 0, c->stream, proj,
                      nl.sup_node.ptr, nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr,
-                     nl.atom_npj.ptr, nl.max_pj, X, ldx, n_vec, partial);
+                     nl.atom_npj.ptr, nl.max_pj, n_work, nct, X, ldx, n_vec, partial);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(nl_couple_kernel<T>, dim3(nl.n_atoms, nct), dim3(64), 0, c->stream, partial,
-                     nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.delta.ptr, nl.max_pj, n_vec, alpha, Cp);
+  hipLaunchKernelGGL(nl_reduce_kernel<T>, dim3(nl.n_atoms, mr, nct), dim3(64), 0, c->stream, partial,
+                     nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.max_pj, n_vec, Csum);
   LAUNCH_CHECK();
-  const int nb = cdiv(nl.n_unodes, 4);
-  hipLaunchKernelGGL(nl_scatter_kernel<T>, dim3(nb), dim3(256), 0, c->stream, proj, nl.unode.ptr,
-                     nl.unode_off.ptr, nl.ulist_entry.ptr, nl.ulist_atom.ptr, nl.atom_npj.ptr,
-                     nl.max_pj, nl.n_unodes, Cp, n_vec, W, ldw);
+  hipLaunchKernelGGL(nl_delta_kernel<T>, dim3(nl.n_atoms, nct), dim3(64), 0, c->stream, Csum,
+                     nl.atom_npj.ptr, nl.delta.ptr, nl.max_pj, n_vec, alpha, Cp);
+  LAUNCH_CHECK();
+  return Cp;
+}
+
+template <class T>
+static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<T>::type* proj,
+                                 const typename C2<T>::type* Cp, const double2* X, int64_t ldx,
+                                 double2* W, int64_t ldw, const double2* Wold, int64_t ldo, int n_vec,
+                                 double beta, double gamma) {
+  const int64_t rows = 2 * c->n_nodes;
+  StageTimer tm(c, CHFSI_STAGE_AXPY, Cp ? 8.0 * 2.0 * nl.n_entries * nl.max_pj * n_vec : 0.0, 0.0,
+                (double)rows * n_vec * sizeof(double2) * (1.0 + (beta != 0.0) + (gamma != 0.0)));
+  const int has = Cp != nullptr;
+  dim3 grid(cdiv(c->n_nodes, 4), cdiv(n_vec, 128));
+  hipLaunchKernelGGL(init_nl_kernel<T>, grid, dim3(256), 0, c->stream, proj,
+                     has ? nl.node_off.ptr : nullptr, has ? nl.nlist_entry.ptr : nullptr,
+                     has ? nl.nlist_atom.ptr : nullptr, has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has,
+                     X, ldx, W, ldw, Wold, ldo, c->n_nodes, n_vec, beta, gamma);
   LAUNCH_CHECK();
 }
 
-void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-             int n_vec, int prec, double alpha, double beta, double gamma) {
-  const int64_t rows = 2 * c->n_nodes;
-  launch_axpby_rows(c, W, ldw, X, ldx, rows, n_vec, beta, gamma);
+void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+              const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta,
+              double gamma) {
   if (prec == CHFSI_PREC_MIXED) {
-    nonlocal_apply<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, W, ldw, n_vec, alpha);
+    const float2* Cp = nonlocal_coeffs<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, n_vec, alpha);
+    init_and_backproduct<float>(c, kp.nl, kp.nl.proj32.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta,
+                                gamma);
     if (kp.gamma)
       launch_cells_cb<float, false>(c, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
     else
       launch_cells_cb<float, true>(c, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
   } else {
-    nonlocal_apply<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, W, ldw, n_vec, alpha);
+    const double2* Cp = nonlocal_coeffs<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, n_vec, alpha);
+    init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta,
+                                 gamma);
     if (kp.gamma)
       launch_cells_cb<double, false>(c, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
     else
       launch_cells_cb<double, true>(c, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
   }
+}
+
+void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+             int n_vec, int prec, double alpha, double beta, double gamma) {
+  apply_H2(c, kp, X, ldx, W, ldw, W, ldw, n_vec, prec, alpha, beta, gamma);
+}
+
+// ============================================================================
+// Adjoint: fields at the quadrature points and their cross densities
+// ============================================================================
+// One block per cell.  For CC columns at a time, the M^{-1/2}-scaled cell rows
+// of L and Y (both spins) are gathered into LDS and interpolated to the
+// quadrature points by sum factorisation over x, y, z (N_i = l_ax l_ay l_az);
+// each thread then owns up to four points and accumulates, over all columns,
+//   Re l^H y,  Re l^H sigma_x y,  Re l^H sigma_y y,  Re l^H sigma_z y.
+constexpr int kCdMaxQ = 4;   // points per thread: nq^3 <= 1024
+__global__ __launch_bounds__(256) void cross_density_kernel(
+    const double2* __restrict__ L, int64_t ldl, const double2* __restrict__ Y, int64_t ldy, int n_vec,
+    const int32_t* __restrict__ cell_nodes, const double* __restrict__ minv_sqrt,
+    const double* __restrict__ B1, const double* __restrict__ wq1, double J, int np1, int nq, int nloc,
+    int maxsz, int CC, double alpha, double* __restrict__ dV, double* __restrict__ dB) {
+  extern __shared__ double2 sm[];
+  double2* bufA = sm;                               // [CC*4][maxsz]
+  double2* bufB = sm + (size_t)CC * 4 * maxsz;      // [CC*4][maxsz]
+  double* sBt = reinterpret_cast<double*>(bufB + (size_t)CC * 4 * maxsz);   // [np1][nq]
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int nq3 = nq * nq * nq;
+  for (int t = tid; t < np1 * nq; t += 256) sBt[t] = B1[t];
+  double acc[kCdMaxQ][4];
+#pragma unroll
+  for (int i = 0; i < kCdMaxQ; ++i) acc[i][0] = acc[i][1] = acc[i][2] = acc[i][3] = 0.0;
+  const int32_t* nodes = cell_nodes + (size_t)e * nloc;
+  for (int n0 = 0; n0 < n_vec; n0 += CC) {
+    // gather: stream s = 2 * operand + spin
+    for (int t = tid; t < CC * 4 * nloc; t += 256) {
+      const int i = t % nloc, s = (t / nloc) % 4, cc = t / (4 * nloc);
+      const int col = n0 + cc;
+      double2 v = {0.0, 0.0};
+      if (col < n_vec) {
+        const int64_t I = nodes[i];
+        const int64_t r = 2 * I + (s & 1);
+        const double sc = minv_sqrt[I];
+        const double2 z = (s < 2) ? L[r * ldl + col] : Y[r * ldy + col];
+        v.x = sc * z.x;
+        v.y = sc * z.y;
+      }
+      bufA[(size_t)(cc * 4 + s) * maxsz + i] = v;
+    }
+    __syncthreads();
+    // x: T1[qx + nq (ay + np az)] = sum_ax l_ax(qx) Z[ax + np (ay + np az)]
+    for (int t = tid; t < CC * 4 * nq * np1 * np1; t += 256) {
+      const int o = t % (nq * np1 * np1), st = t / (nq * np1 * np1);
+      const int qx = o % nq, rest = o / nq;
+      const double2* in = bufA + (size_t)st * maxsz + rest * np1;
+      double2 v = {0.0, 0.0};
+      for (int ax = 0; ax < np1; ++ax) {
+        const double b = sBt[ax * nq + qx];
+        v.x += b * in[ax].x;
+        v.y += b * in[ax].y;
+      }
+      bufB[(size_t)st * maxsz + o] = v;
+    }
+    __syncthreads();
+    // y: T2[qx + nq (qy + nq az)] = sum_ay l_ay(qy) T1[qx + nq (ay + np az)]
+    for (int t = tid; t < CC * 4 * nq * nq * np1; t += 256) {
+      const int o = t % (nq * nq * np1), st = t / (nq * nq * np1);
+      const int qx = o % nq, qy = (o / nq) % nq, az = o / (nq * nq);
+      const double2* in = bufB + (size_t)st * maxsz;
+      double2 v = {0.0, 0.0};
+      for (int ay = 0; ay < np1; ++ay) {
+        const double b = sBt[ay * nq + qy];
+        const double2 z = in[qx + nq * (ay + np1 * az)];
+        v.x += b * z.x;
+        v.y += b * z.y;
+      }
+      bufA[(size_t)st * maxsz + o] = v;
+    }
+    __syncthreads();
+    // z: Zq[qx + nq (qy + nq qz)] = sum_az l_az(qz) T2[qx + nq (qy + nq az)]
+    for (int t = tid; t < CC * 4 * nq3; t += 256) {
+      const int o = t % nq3, st = t / nq3;
+      const int qxy = o % (nq * nq), qz = o / (nq * nq);
+      const double2* in = bufA + (size_t)st * maxsz;
+      double2 v = {0.0, 0.0};
+      for (int az = 0; az < np1; ++az) {
+        const double b = sBt[az * nq + qz];
+        const double2 z = in[qxy + nq * nq * az];
+        v.x += b * z.x;
+        v.y += b * z.y;
+      }
+      bufB[(size_t)st * maxsz + o] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qi = 0; qi < kCdMaxQ; ++qi) {
+      const int q = tid + 256 * qi;
+      if (q >= nq3) continue;
+      for (int cc = 0; cc < CC; ++cc) {
+        const double2 l0 = bufB[(size_t)(cc * 4 + 0) * maxsz + q], l1 = bufB[(size_t)(cc * 4 + 1) * maxsz + q];
+        const double2 y0 = bufB[(size_t)(cc * 4 + 2) * maxsz + q], y1 = bufB[(size_t)(cc * 4 + 3) * maxsz + q];
+        // conj(l_a) y_b = (lr - i li)(yr + i yi)
+        const double r00 = l0.x * y0.x + l0.y * y0.y, i00 = l0.x * y0.y - l0.y * y0.x;
+        const double r11 = l1.x * y1.x + l1.y * y1.y, i11 = l1.x * y1.y - l1.y * y1.x;
+        const double r01 = l0.x * y1.x + l0.y * y1.y, i01 = l0.x * y1.y - l0.y * y1.x;
+        const double r10 = l1.x * y0.x + l1.y * y0.y, i10 = l1.x * y0.y - l1.y * y0.x;
+        (void)i00;
+        (void)i11;
+        acc[qi][0] += r00 + r11;          // 1
+        acc[qi][1] += r01 + r10;          // sigma_x
+        acc[qi][2] += i01 - i10;          // sigma_y: Re(conj(l0)(-i y1) + conj(l1)(i y0))
+        acc[qi][3] += r00 - r11;          // sigma_z
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int qi = 0; qi < kCdMaxQ; ++qi) {
+    const int q = tid + 256 * qi;
+    if (q >= nq3) continue;
+    const int qx = q % nq, qy = (q / nq) % nq, qz = q / (nq * nq);
+    const double w = alpha * wq1[qx] * wq1[qy] * wq1[qz] * J;
+    const size_t eq = (size_t)e * nq3 + q;
+    dV[eq] += w * acc[qi][0];
+    dB[eq * 3 + 0] += w * acc[qi][1];
+    dB[eq * 3 + 1] += w * acc[qi][2];
+    dB[eq * 3 + 2] += w * acc[qi][3];
+  }
+}
+
+void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
+                   double alpha, double* dV, double* dB) {
+  const int np1 = c->np1, nq = c->nq;
+  const int maxsz = std::max(std::max(c->nloc, nq * np1 * np1), std::max(nq * nq * np1, c->nq3));
+  CHFSI_CHECK(c->nq3 <= 256 * kCdMaxQ, CHFSI_EINVAL, "adjoint supports n_q <= 10");
+  const size_t per_cc = 2 * 4 * (size_t)maxsz * sizeof(double2);
+  const size_t budget = 128 * 1024;
+  const int CC = (int)std::max<size_t>(1, std::min<size_t>(4, budget / per_cc));
+  const size_t sh = CC * per_cc + np1 * nq * sizeof(double);
+  CHFSI_CHECK(sh <= 160 * 1024, CHFSI_EINVAL, "adjoint: cell too large for LDS");
+  DevBuf<double> b1, wq;
+  b1.upload(c->ref.B.data(), c->ref.B.size(), c->stream);
+  wq.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
+  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, 2.0 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
+  hipLaunchKernelGGL(cross_density_kernel, dim3(c->n_cells), dim3(256), sh, c->stream, L, ldl, Y, ldy, n_vec,
+                     c->cell_nodes.ptr, c->minv_sqrt.ptr, b1.ptr, wq.ptr, c->J, np1, nq, c->nloc, maxsz, CC,
+                     alpha, dV, dB);
+  LAUNCH_CHECK();
+  CHFSI_HIP(hipStreamSynchronize(c->stream));   // b1, wq leave scope
 }
 
 // ============================================================================

@@ -9,6 +9,7 @@ import scipy.sparse as sp
 
 import synth
 from oracle import fe, hamiltonian as ham, projectors
+from closed_forms import periodic_1d as _periodic_1d
 
 
 def _const_fields(mesh, v0=0.0, bvec=(0.0, 0.0, 0.0)):
@@ -78,28 +79,6 @@ def test_free_electron_constant_mode_exact(quad):
         assert np.abs(y[:, 0] - lam * x).max() < 1e-12 * np.abs(x).max() * 10
     ev = np.linalg.eigvalsh(H.toarray())
     assert abs(ev[0] - (0.5 * k @ k - 0.7 - bmag)) < 1e-11
-
-
-def _periodic_1d(ncell, L, p, k):
-    """1-D periodic spectral-element operator with GLL collocation:
-    M^{-1/2} (1/2 K - i k C + k^2/2 M) M^{-1/2}."""
-    xi, w = fe.gauss_lobatto(p)
-    _, D = fe.lagrange_tables(xi, xi)       # D[i, q] = l_i'(xi_q)
-    h = L / ncell
-    n = ncell * p
-    K = np.zeros((n, n)); C = np.zeros((n, n)); M = np.zeros(n)
-    for c in range(ncell):
-        g = (c * p + np.arange(p + 1)) % n
-        Kc = (2 / h) * (D * w) @ D.T                     # sum_q w_q (h/2)(2/h)^2 l_i' l_j'
-        Cc = np.diag(w) @ D.T                            # sum_q w_q (h/2) l_i (2/h) l_j'
-        for a in range(p + 1):
-            M[g[a]] += w[a] * h / 2
-            for b in range(p + 1):
-                K[g[a], g[b]] += Kc[a, b]
-                C[g[a], g[b]] += Cc[a, b]
-    A = 0.5 * K - 1j * k * C + 0.5 * k * k * np.diag(M)
-    s = 1 / np.sqrt(M)
-    return s[:, None] * A * s[None, :]
 
 
 def test_gll_mode_separable_spectrum_with_k_field_and_shift():
