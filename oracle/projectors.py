@@ -139,7 +139,8 @@ def bloch_projector(atom, pts: np.ndarray, k, box) -> np.ndarray:
     L = np.asarray(box, dtype=np.float64)
     R = np.asarray(atom.pos, dtype=np.float64)
     k = np.asarray(k, dtype=np.float64)
-    nimg = [int(math.ceil(atom.rcut / L[d])) + 1 for d in range(3)]
+    # points and atoms lie in [0, L): an image n contributes only if |n| L < L + r_c
+    nimg = [int(math.ceil(atom.rcut / L[d])) for d in range(3)]
     out = np.zeros((pts.shape[0], n_orbitals(atom)), dtype=np.complex128)
     for ix in range(-nimg[0], nimg[0] + 1):
         for iy in range(-nimg[1], nimg[1] + 1):

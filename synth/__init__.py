@@ -67,6 +67,16 @@ def random_block(seed: int, n_rows: int, n_cols: int, row0: int = 0,
     return re + 1j * im
 
 
+def random_rows(seed: int, rows, n_cols: int, n_total_cols: Optional[int] = None,
+                col0: int = 0) -> np.ndarray:
+    """Arbitrary rows of the same seeded multivector as random_block."""
+    ntc = n_cols if n_total_cols is None else n_total_cols
+    r = np.asarray(rows, dtype=np.uint64)[:, None]
+    n = np.arange(col0, col0 + n_cols, dtype=np.uint64)[None, :]
+    j = r * np.uint64(ntc) + n
+    return uniform_pm1(seed, np.uint64(2) * j) + 1j * uniform_pm1(seed, np.uint64(2) * j + np.uint64(1))
+
+
 # --------------------------------------------------------------------------
 # System description
 # --------------------------------------------------------------------------

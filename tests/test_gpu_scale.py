@@ -72,3 +72,60 @@ def test_gll_kronecker_eigenvectors_full_scale(k):
     print(f"[scale gll k={k}] mixed rel residual = {errm:.3e}", flush=True)
     assert errm < 2e-6
     op.close()
+
+
+def _sample_nodes(s, rng, n_near=48, n_far=16):
+    """Nodes within r_c/2 of the first atom and of the last atom (opposite
+    corners of the box, so different cells and colours)."""
+    from oracle.fe import Mesh
+    mesh = Mesh(s.n_cells, s.box, s.p, s.quad, s.n_q)
+    cand = rng.choice(s.n_nodes, 400000, replace=False)
+    Nx, Ny, _ = mesh.N
+    idx = np.stack([cand % Nx, (cand // Nx) % Ny, cand // (Nx * Ny)], axis=1)
+    xyz = np.stack([(idx[:, d] // s.p) * mesh.h[d] + (mesh.xi[idx[:, d] % s.p] + 1) * mesh.h[d] / 2
+                    for d in range(3)], axis=1)
+    L = np.asarray(s.box)
+    dist = []
+    for a in s.atoms:
+        d = xyz - np.asarray(a.pos)
+        d = d - L * np.round(d / L)
+        dist.append(np.linalg.norm(d, axis=1))
+    dist = np.stack(dist)
+    near = cand[dist[0] < s.atoms[0].rcut / 2][:n_near]
+    far = cand[dist[-1] < s.atoms[-1].rcut / 2][:n_far]
+    return np.sort(np.concatenate([near, far]))
+
+
+def test_scale_workload_sampled_rows():
+    """The large workload (20^3 cells, p=6, 64 SOC atoms, N = 128 as timed by the
+    benchmark): rows of H_hat X from the oracle, cell by cell, at sampled nodes."""
+    import synth
+    from oracle import rows
+    from paper_2410_02754_amd import Operator
+    s = synth.config("scale")
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts)
+    pts = op.quad_points().reshape(-1, 3)
+    V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+    B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+    op.set_local(V, B)
+    op.set_atoms(s.atoms)
+    del V, B, pts
+    n_vec = 128
+    X = torch.empty((s.n_dof, n_vec), dtype=torch.complex128, device="cuda")
+    op.fill_random(X, s.seed, n_total_cols=n_vec)
+    Y = torch.empty_like(X)
+    op.apply_H(X, Y)
+    Ym = torch.empty_like(X)
+    op.apply_H(X, Ym, prec="mixed")
+    nodes = _sample_nodes(s, np.random.default_rng(11))
+    rr = torch.tensor(np.stack([2 * nodes, 2 * nodes + 1], axis=1).ravel(), device="cuda")
+    got = Y[rr].cpu().numpy().reshape(len(nodes), 2, n_vec)
+    gotm = Ym[rr].cpu().numpy().reshape(len(nodes), 2, n_vec)
+    del X, Y, Ym
+    op.close()
+    ref = rows.apply_rows(s, nodes, lambda r: synth.random_rows(s.seed, r, n_vec, n_vec), synth.veff, synth.bxc)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    errm = np.abs(gotm - ref).max() / np.abs(ref).max()
+    print(f"[scale rows] {len(nodes)} nodes: fp64 rel err {err:.3e}, mixed {errm:.3e}", flush=True)
+    assert err < 1e-12
+    assert errm < 2e-6

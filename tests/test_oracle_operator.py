@@ -217,3 +217,17 @@ def test_kramers_degeneracy_and_k_symmetry():
     wm = np.linalg.eigvalsh(ham.build(s2, synth.veff, synth.bxc, ik=1)[1].toarray())
     assert np.abs(wp - wm).max() < 1e-11
     assert np.abs(wp[0::2] - wp[1::2]).max() > 1e-6    # B=0, k != 0: no Kramers pairing at k
+
+
+def test_row_sampled_apply_equals_assembled():
+    """oracle.rows (for meshes too large to assemble) against the assembled operator."""
+    from oracle import rows
+    s = synth.make_system("r", n_cells=(3, 2, 3), box=(5.0, 4.0, 5.0), p=3, kpts=[(0.1, 0.05, -0.1)],
+                          n_atoms=2, lmax=2, rcut_sigmas=5.0)
+    _, H, MD, V, B = ham.build(s, synth.veff, synth.bxc)
+    X = synth.random_block(3, s.n_dof, 5)
+    ref = H @ X
+    nodes = np.array([0, 7, 13, 101, s.n_nodes - 1])
+    got = rows.apply_rows(s, nodes, lambda r: X[r], synth.veff, synth.bxc)
+    exp = np.stack([ref[2 * nodes], ref[2 * nodes + 1]], axis=1)
+    assert np.abs(got - exp).max() < 1e-13 * np.abs(exp).max()
