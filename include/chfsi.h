@@ -200,6 +200,50 @@ int chfsi_cheb_filter_backward(chfsi_ctx* ctx, int ik, const void* X_d, int64_t 
                                double b, double a0, int ckpt_every, void* work_d, size_t work_bytes,
                                double* dV_d, double* dB_d);
 
+/* ---- Batched filtering of independent operators (the k-points of a grid and
+ * independent systems: the eigenproblems of different k are independent,
+ * Sec. III.B).  One task = one (context, k-point, block): X_d [2M][ldx] is
+ * filtered in place with work_d [2M][ldw].  Per recurrence step the projector
+ * terms run per task and the cell products of all tasks run as one persistent
+ * launch per colour phase (per tile width and k-term variant).  Tasks may share
+ * a context (k-points of one mesh) but not X or work buffers. */
+typedef struct chfsi_batch chfsi_batch;
+typedef struct {
+  chfsi_ctx* ctx;
+  int ik;
+  void* X_d;
+  int64_t ldx;
+  void* work_d;
+  int64_t ldw;
+  int n_vec;
+} chfsi_batch_task;
+enum chfsi_batch_flags {
+  CHFSI_BATCH_AUTOTUNE = 1,  /* time column tile widths 32/64/128 per task at create, keep the fastest */
+  CHFSI_BATCH_GRAPH = 2      /* capture the whole filter into a hipGraph and replay it while the bounds
+                                are unchanged (needs a non-default stream) */
+};
+
+/* Build a batch of n_tasks tasks for a degree-m filter in precision prec_mode.
+ * All contexts must share one stream and have their fields set.  Buffers are
+ * bound at creation.  With CHFSI_BATCH_AUTOTUNE the work buffers are used as
+ * scratch during creation. */
+int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, int prec_mode, int flags,
+                       chfsi_batch** out);
+
+/* Filter every task's block with its own bounds a[t], b[t], a0[t] (host arrays,
+ * a0 < a < b): the same scaled recurrence as chfsi_cheb_filter.  Asynchronous. */
+int chfsi_batch_filter(chfsi_batch* batch, const double* a, const double* b, const double* a0);
+
+/* Chosen column tile width per task (cols_out[n_tasks]) and, if tune_ms is not
+ * NULL, the timed cell-stage milliseconds for widths 32, 64, 128 (-1 = not run). */
+int chfsi_batch_tiles(const chfsi_batch* batch, int* cols_out, double* tune_ms);
+
+/* Free the batch (not the contexts or buffers).  batch may be NULL. */
+int chfsi_batch_destroy(chfsi_batch* batch);
+
+/* Text of the batch's most recent error. */
+const char* chfsi_batch_last_error(const chfsi_batch* batch);
+
 /* Fill rows [row0, row0+n_rows) x columns [col0, col0+n_vec) of a seeded
  * [..][n_total_cols] multivector into X_d [n_rows][ld]:
  * X[r][n] = u(2j) + i u(2j+1), j = r * n_total_cols + n, u(i) = 2 w - 1 with w

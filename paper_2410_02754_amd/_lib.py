@@ -15,7 +15,8 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_rayleigh_ritz", "chfsi_lanczos_bounds", "chfsi_fill_random", "chfsi_sync",
             "chfsi_last_error", "chfsi_version", "chfsi_stats_enable", "chfsi_stats_read",
             "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
-            "chfsi_cheb_filter_backward"]
+            "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
+            "chfsi_batch_destroy", "chfsi_batch_last_error"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -30,6 +31,11 @@ class AtomDesc(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("lmax", C.c_int), ("sigma", C.c_double),
                 ("rcut", C.c_double), ("d0", C.c_double * 3), ("dso", C.c_double),
                 ("delta_override", C.POINTER(C.c_double))]
+
+
+class BatchTask(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("ik", C.c_int), ("X_d", C.c_void_p), ("ldx", C.c_int64),
+                ("work_d", C.c_void_p), ("ldw", C.c_int64), ("n_vec", C.c_int)]
 
 
 class StageStats(C.Structure):
@@ -75,6 +81,11 @@ def load():
         "chfsi_lanczos_bounds": ([vp, i32, i32, vp, pd, pd], i32),
         "chfsi_fill_random": ([vp, vp, i64, i32, i64, C.c_uint64, i64, i32, i64], i32),
         "chfsi_sync": ([vp], i32),
+        "chfsi_batch_create": ([i32, C.POINTER(BatchTask), i32, i32, i32, C.POINTER(vp)], i32),
+        "chfsi_batch_filter": ([vp, pd, pd, pd], i32),
+        "chfsi_batch_tiles": ([vp, C.POINTER(i32), pd], i32),
+        "chfsi_batch_destroy": ([vp], i32),
+        "chfsi_batch_last_error": ([vp], C.c_char_p),
         "chfsi_apply_H_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, vp, vp], i32),
         "chfsi_filter_backward_workspace": ([vp, i32, i32, i32], C.c_size_t),
         "chfsi_cheb_filter_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, i32, dbl, dbl, dbl,

@@ -228,3 +228,59 @@ class Operator:
 
     def sync(self):
         self._chk(self.lib.chfsi_sync(self.ctx))
+
+
+BATCH_AUTOTUNE = 1
+BATCH_GRAPH = 2
+
+
+class Batch:
+    """Batched filter of many (operator, k-point, block) tasks; see chfsi_batch_create.
+    tasks: list of (Operator, ik, X, work) with X, work complex128 CUDA blocks."""
+
+    def __init__(self, tasks, degree: int, prec="fp64", flags: int = BATCH_AUTOTUNE | BATCH_GRAPH):
+        self.lib = _lib.load()
+        self._keep = tasks
+        arr = (_lib.BatchTask * len(tasks))()
+        for i, (op, ik, X, W) in enumerate(tasks):
+            px, ldx, n = _block(X, "X")
+            pw, ldw, nw = _block(W, "work")
+            if nw < n:
+                raise ValueError("work narrower than X")
+            arr[i].ctx = op.ctx
+            arr[i].ik = int(ik)
+            arr[i].X_d = px
+            arr[i].ldx = ldx
+            arr[i].work_d = pw
+            arr[i].ldw = ldw
+            arr[i].n_vec = n
+        h = C.c_void_p()
+        rc = self.lib.chfsi_batch_create(len(tasks), arr, int(degree), _PREC[prec], int(flags), C.byref(h))
+        if rc != 0:
+            raise _lib.ChfsiError(rc, "chfsi_batch_create failed (check contexts, buffers, stream)")
+        self.h = h
+        self.n = len(tasks)
+
+    def filter(self, a, b, a0):
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (self.n,))) for v in (a, b, a0)]
+        ptrs = [x.ctypes.data_as(C.POINTER(C.c_double)) for x in arrs]
+        rc = self.lib.chfsi_batch_filter(self.h, *ptrs)
+        if rc != 0:
+            raise _lib.ChfsiError(rc, self.lib.chfsi_batch_last_error(self.h).decode())
+
+    def tiles(self):
+        cols = (C.c_int * self.n)()
+        ms = np.zeros(3 * self.n)
+        self.lib.chfsi_batch_tiles(self.h, cols, ms.ctypes.data_as(C.POINTER(C.c_double)))
+        return list(cols), ms.reshape(self.n, 3)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chfsi_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

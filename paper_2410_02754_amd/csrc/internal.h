@@ -125,6 +125,17 @@ struct KPoint {
   NonlocalK nl;
 };
 
+// Device descriptor of one task of a batched filter (see batch.cpp).
+struct BatchTaskDev {
+  const double* cm64;
+  const float* cm32;
+  const int32_t* cell_nodes;
+  double2* buf[2];
+  int64_t ld[2];
+  int n_vec, nloc, nrb, nkb, nmat;
+  int pad;
+};
+
 struct StageRec {
   int stage;
   hipEvent_t start, stop;
@@ -222,6 +233,15 @@ void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n,
 void column_resid_norms(chfsi_ctx* c, const double2* W, int64_t ldw, const double2* X, int64_t ldx,
                         int64_t rows, int n, const double* theta, double* out);
 double dot_re(chfsi_ctx* c, const double2* x, const double2* y, int64_t rows);
+// batched filter support (kernels.hip)
+void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const BatchTaskDev* tasks, const int4* items,
+                       int n_items, const double* alpha, int src, int grid);
+int cell_batch_blocks_per_cu(bool fp64, int CB, bool has_s);
+double time_cell_stage(chfsi_ctx* c, KPoint& kp, int CB, int prec, const double2* X, int64_t ldx, double2* W,
+                       int64_t ldw, int n_vec, int reps);
+void nonlocal_prepare(chfsi_ctx* c, KPoint& kp, int n_vec);   // size scratch for apply_H of this width
+void apply_nonlocal_init(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+                         int n_vec, int prec, double alpha, double beta, double gamma);
 void launch_fill_random(chfsi_ctx* c, double2* X, int64_t n_rows, int n_vec, int64_t ld,
                         uint64_t seed, int64_t row0, int col0, int64_t n_total_cols);
 }  // namespace chfsi

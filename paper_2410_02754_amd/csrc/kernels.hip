@@ -166,33 +166,33 @@ void launch_cell_to_f32(chfsi_ctx* c, KPoint& kp) {
 // cell operator.  Per 4-node k-step and 16-column block the products are
 //   Yup_r += Hp a + Bx c + By d - S b      Yup_i += Hp b + Bx d - By c + S a
 //   Ydn_r += Hm c + Bx a - By b - S d      Ydn_i += Hm d + Bx b + By a + S c
+template <class T, int CB>
+struct CellSmem {
+  static constexpr int BN = 32 * CB;
+  static constexpr int BK = 8;
+  static constexpr int PAD = 16;          // row pad: 4 k-rows of a fragment hit disjoint banks
+  T sB[2][4][BK][BN + PAD];
+  int32_t sNode[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
+};
+
+// One block tile of the fused gather / cell product / scatter-add for cell e,
+// row tile rt (two 16-row blocks) and column tile ct.  Starts and ends with
+// the block synchronised, so it can be called repeatedly by a persistent block.
 template <class T, int CB, bool HAS_S>
-__global__ __launch_bounds__(256) void cell_apply_kernel(
-    const T* __restrict__ cm, const int32_t* __restrict__ cell_nodes,
-    const int32_t* __restrict__ cells, int nloc, int nrb, int nkb, int nmat, int n_rowtiles,
-    int n_coltiles, int n_work, const double2* __restrict__ X, int64_t ldx, double2* __restrict__ W,
-    int64_t ldw, int n_vec, double alpha) {
+__device__ __forceinline__ void cell_tile(CellSmem<T, CB>& sm, const T* __restrict__ cm,
+                                          const int32_t* __restrict__ cell_nodes, int e, int rt, int ct,
+                                          int nloc, int nrb, int nkb, int nmat,
+                                          const double2* __restrict__ X, int64_t ldx,
+                                          double2* __restrict__ W, int64_t ldw, int n_vec, double alpha) {
   typedef typename Vec4<T>::type V4;
   constexpr int BN = 32 * CB;
   constexpr int BK = 8;
-  constexpr int PAD = 16;                 // row pad: 4 k-rows of a fragment hit disjoint banks
   constexpr int NPRE = (BK * 2 * BN) / 256;
   constexpr int NM = HAS_S ? 5 : 4;
-  __shared__ T sB[2][4][BK][BN + PAD];
-  __shared__ int32_t sNode[(kMaxP + 1) * (kMaxP + 1) * (kMaxP + 1)];
-
-  // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
-  // XCD gets a contiguous range of (cell, row tile, column tile) work and the
-  // row tiles of one cell share that XCD's L2 for the gathered rows.
-  const int per_xcd = (n_work + 7) / 8;
-  const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-  if (bid >= n_work) return;              // uniform over the block, before any barrier
-
+  auto& sB = sm.sB;
+  auto& sNode = sm.sNode;
+  __syncthreads();                        // previous tile's LDS reads are done
   const int tid = threadIdx.x;
-  const int ct = bid % n_coltiles;
-  const int rt = (bid / n_coltiles) % n_rowtiles;
-  const int ci = bid / (n_coltiles * n_rowtiles);
-  const int e = cells[ci];
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave & 1, wc = wave >> 1;
   const int rb = rt * 2 + wr;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
       for (int m = 0; m < NM; ++m) aC[kk][m] = aN[kk][m];
   }
 
-  if (!row_active) return;
+  if (!row_active) return;                // (no barrier follows inside the tile)
   // epilogue: lane holds rows acc_row(lane, j), column lane%16 of each 16x16 tile
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -330,6 +330,47 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
       w0[gcol] = o0;
       w1[gcol] = o1;
     }
+  }
+}
+
+
+template <class T, int CB, bool HAS_S>
+__global__ __launch_bounds__(256) void cell_apply_kernel(
+    const T* __restrict__ cm, const int32_t* __restrict__ cell_nodes,
+    const int32_t* __restrict__ cells, int nloc, int nrb, int nkb, int nmat, int n_rowtiles,
+    int n_coltiles, int n_work, const double2* __restrict__ X, int64_t ldx, double2* __restrict__ W,
+    int64_t ldw, int n_vec, double alpha) {
+  __shared__ CellSmem<T, CB> sm;
+  // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+  // XCD gets a contiguous range of (cell, row tile, column tile) work and the
+  // row tiles of one cell share that XCD's L2 for the gathered rows.
+  const int per_xcd = (n_work + 7) / 8;
+  const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (bid >= n_work) return;              // uniform over the block, before any barrier
+  const int ct = bid % n_coltiles;
+  const int rt = (bid / n_coltiles) % n_rowtiles;
+  const int ci = bid / (n_coltiles * n_rowtiles);
+  cell_tile<T, CB, HAS_S>(sm, cm, cell_nodes, cells[ci], rt, ct, nloc, nrb, nkb, nmat, X, ldx, W, ldw, n_vec,
+                          alpha);
+}
+
+// Batched form: one persistent grid walks a static list of (task, cell, row
+// tile, column tile) items of one colour phase across many independent
+// operators (k-points, systems).  Items were ordered on the host so that item
+// i runs on XCD i % 8 and the row tiles of a cell share an XCD.
+
+template <class T, int CB, bool HAS_S>
+__global__ __launch_bounds__(256) void cell_batch_kernel(const BatchTaskDev* __restrict__ tasks,
+                                                         const int4* __restrict__ items, int n_items,
+                                                         const double* __restrict__ alpha, int src) {
+  __shared__ CellSmem<T, CB> sm;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 w = items[it];
+    if (w.x < 0) continue;                // padding item (uniform over the block)
+    const BatchTaskDev& t = tasks[w.x];
+    const T* cm = sizeof(T) == 8 ? (const T*)t.cm64 : (const T*)t.cm32;
+    cell_tile<T, CB, HAS_S>(sm, cm, t.cell_nodes, w.y, w.z, w.w, t.nloc, t.nrb, t.nkb, t.nmat, t.buf[src],
+                            t.ld[src], t.buf[src ^ 1], t.ld[src ^ 1], t.n_vec, alpha[w.x]);
   }
 }
 
@@ -741,6 +782,110 @@ void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* 
 void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
              int n_vec, int prec, double alpha, double beta, double gamma) {
   apply_H2(c, kp, X, ldx, W, ldw, W, ldw, n_vec, prec, alpha, beta, gamma);
+}
+
+// ---------------------------------------------------------------- batched support
+void apply_nonlocal_init(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+                         int n_vec, int prec, double alpha, double beta, double gamma) {
+  if (prec == CHFSI_PREC_MIXED) {
+    const float2* Cp = nonlocal_coeffs<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, n_vec, alpha);
+    init_and_backproduct<float>(c, kp.nl, kp.nl.proj32.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma);
+  } else {
+    const double2* Cp = nonlocal_coeffs<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, n_vec, alpha);
+    init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma);
+  }
+}
+
+void nonlocal_prepare(chfsi_ctx* c, KPoint& kp, int n_vec) {
+  const NonlocalK& nl = kp.nl;
+  if (nl.n_atoms == 0 || nl.n_entries == 0) return;
+  const size_t mr = 2 * nl.max_pj;
+  const size_t n = (size_t)nl.n_chunks * mr * n_vec + 2 * (size_t)nl.n_atoms * mr * n_vec;
+  c->scratch.alloc(2 * n);     // double2 elements, the larger of the two precisions
+}
+
+template <class T, int CB, bool HAS_S>
+static void launch_batch_t(hipStream_t s, const BatchTaskDev* tasks, const int4* items, int n_items,
+                           const double* alpha, int src, int grid) {
+  hipLaunchKernelGGL((cell_batch_kernel<T, CB, HAS_S>), dim3(grid), dim3(256), 0, s, tasks, items, n_items, alpha,
+                     src);
+  LAUNCH_CHECK();
+}
+
+template <class T, bool HAS_S>
+static void launch_batch_cb(hipStream_t s, int CB, const BatchTaskDev* tasks, const int4* items, int n_items,
+                            const double* alpha, int src, int grid) {
+  if (CB == 4)
+    launch_batch_t<T, 4, HAS_S>(s, tasks, items, n_items, alpha, src, grid);
+  else if (CB == 2)
+    launch_batch_t<T, 2, HAS_S>(s, tasks, items, n_items, alpha, src, grid);
+  else
+    launch_batch_t<T, 1, HAS_S>(s, tasks, items, n_items, alpha, src, grid);
+}
+
+void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const BatchTaskDev* tasks, const int4* items,
+                       int n_items, const double* alpha, int src, int grid) {
+  if (fp64) {
+    if (has_s) launch_batch_cb<double, true>(s, CB, tasks, items, n_items, alpha, src, grid);
+    else launch_batch_cb<double, false>(s, CB, tasks, items, n_items, alpha, src, grid);
+  } else {
+    if (has_s) launch_batch_cb<float, true>(s, CB, tasks, items, n_items, alpha, src, grid);
+    else launch_batch_cb<float, false>(s, CB, tasks, items, n_items, alpha, src, grid);
+  }
+}
+
+template <class T, int CB, bool HAS_S>
+static int occ_t() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cell_batch_kernel<T, CB, HAS_S>, 256, 0) != hipSuccess) n = 1;
+  return std::max(1, n);
+}
+
+int cell_batch_blocks_per_cu(bool fp64, int CB, bool has_s) {
+  if (fp64) {
+    if (has_s) return CB == 4 ? occ_t<double, 4, true>() : CB == 2 ? occ_t<double, 2, true>() : occ_t<double, 1, true>();
+    return CB == 4 ? occ_t<double, 4, false>() : CB == 2 ? occ_t<double, 2, false>() : occ_t<double, 1, false>();
+  }
+  if (has_s) return CB == 4 ? occ_t<float, 4, true>() : CB == 2 ? occ_t<float, 2, true>() : occ_t<float, 1, true>();
+  return CB == 4 ? occ_t<float, 4, false>() : CB == 2 ? occ_t<float, 2, false>() : occ_t<float, 1, false>();
+}
+
+template <class T, bool HAS_S>
+static void cells_with_cb(chfsi_ctx* c, int CB, const T* cm, int nmat, const double2* X, int64_t ldx, double2* W,
+                          int64_t ldw, int n_vec) {
+  if (CB == 4) launch_cells<T, 4, HAS_S>(c, cm, nmat, X, ldx, W, ldw, n_vec, 1.0);
+  else if (CB == 2) launch_cells<T, 2, HAS_S>(c, cm, nmat, X, ldx, W, ldw, n_vec, 1.0);
+  else launch_cells<T, 1, HAS_S>(c, cm, nmat, X, ldx, W, ldw, n_vec, 1.0);
+}
+
+// Mean time (ms) of the cell stage of one apply with column tiles of 32*CB.
+double time_cell_stage(chfsi_ctx* c, KPoint& kp, int CB, int prec, const double2* X, int64_t ldx, double2* W,
+                       int64_t ldw, int n_vec, int reps) {
+  const bool was = c->stats_on;
+  c->stats_on = false;
+  hipEvent_t e0, e1;
+  CHFSI_HIP(hipEventCreate(&e0));
+  CHFSI_HIP(hipEventCreate(&e1));
+  auto run = [&]() {
+    if (prec == CHFSI_PREC_MIXED) {
+      if (kp.gamma) cells_with_cb<float, false>(c, CB, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec);
+      else cells_with_cb<float, true>(c, CB, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec);
+    } else {
+      if (kp.gamma) cells_with_cb<double, false>(c, CB, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec);
+      else cells_with_cb<double, true>(c, CB, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec);
+    }
+  };
+  run();                                   // warm
+  CHFSI_HIP(hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps; ++r) run();
+  CHFSI_HIP(hipEventRecord(e1, c->stream));
+  CHFSI_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  CHFSI_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->stats_on = was;
+  return ms / reps;
 }
 
 // ============================================================================

@@ -1,0 +1,126 @@
+"""Batched filter: 8 k-points of a 2x2x2 Monkhorst-Pack grid on one mesh plus
+independent Gamma systems of uneven size and width, in persistent colour-phase
+launches captured in a hipGraph, against per-task chfsi_cheb_filter (bitwise)
+and against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chfsi as och, hamiltonian as ham
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _op(s, stream):
+    from paper_2410_02754_amd import Operator
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts, stream=stream.cuda_stream)
+    pts = op.quad_points().reshape(-1, 3)
+    V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+    B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+    op.set_local(V, B)
+    op.set_atoms(s.atoms)
+    return op
+
+
+def _systems(bmag=0.1):
+    L = 4.8
+    kg = synth.make_system("kg", n_cells=(4, 4, 4), box=(L, L, L), p=3, kpts=synth.monkhorst_pack(2, (L, L, L)),
+                           n_atoms=2, lmax=1, rcut_sigmas=5.0, n_vec=40, b_mag=bmag, seed=1)
+    others = [synth.make_system("u1", n_cells=(2, 2, 2), box=(2.4, 2.4, 2.4), p=3, n_atoms=1, lmax=1,
+                                rcut_sigmas=4.0, n_vec=16, seed=2),
+              synth.make_system("u2", n_cells=(3, 2, 2), box=(3.6, 2.4, 2.4), p=3, n_atoms=1, lmax=2,
+                                rcut_sigmas=4.0, n_vec=70, seed=3)]
+    return kg, others
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_equals_per_task_bitwise(prec):
+    from paper_2410_02754_amd import Batch
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        kg, others = _systems()
+        ops = [_op(kg, stream)] + [_op(s, stream) for s in others]
+        tasks, blocks = [], []
+        for ik in range(8):
+            X = torch.tensor(synth.random_block(10 + ik, kg.n_dof, kg.n_vec), device="cuda")
+            tasks.append((ops[0], ik, X, torch.empty_like(X)))
+        for j, s in enumerate(others):
+            X = torch.tensor(synth.random_block(20 + j, s.n_dof, s.n_vec), device="cuda")
+            tasks.append((ops[1 + j], 0, X, torch.empty_like(X)))
+        X0 = [t[2].clone() for t in tasks]
+        degree = 9
+        bounds = []
+        for op, ik, X, W in tasks:
+            v0 = torch.tensor(synth.lanczos_start(kg, X.shape[0]), device="cuda")
+            lo, hi = op.lanczos_bounds(v0, 20, ik=ik)
+            bounds.append((lo + 0.25 * (hi - lo), hi, lo - 0.5))
+        a, b, a0 = (np.array(v) for v in zip(*bounds))
+        batch = Batch(tasks, degree, prec=prec)
+        cols, tune = batch.tiles()
+        print(f"[batch {prec}] tile widths {cols}", flush=True)
+        batch.filter(a, b, a0)
+        torch.cuda.synchronize()
+        got = [t[2].clone() for t in tasks]
+        # per task, the single-operator filter
+        for i, (op, ik, X, W) in enumerate(tasks):
+            Y = X0[i].clone()
+            op.cheb_filter(Y, torch.empty_like(Y), degree, a[i], b[i], a0[i], ik=ik, prec=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(Y, got[i]), f"task {i} differs"
+        # graph replay with the same bounds, then with new bounds
+        for i, t in enumerate(tasks):
+            t[2].copy_(X0[i])
+        batch.filter(a, b, a0)
+        torch.cuda.synchronize()
+        for i, t in enumerate(tasks):
+            assert torch.equal(t[2], got[i])
+            t[2].copy_(X0[i])
+        batch.filter(a * 0.9 + 0.1 * a0, b, a0)
+        torch.cuda.synchronize()
+        for i, (op, ik, X, W) in enumerate(tasks):
+            Y = X0[i].clone()
+            op.cheb_filter(Y, torch.empty_like(Y), degree, a[i] * 0.9 + 0.1 * a0[i], b[i], a0[i], ik=ik, prec=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(Y, X)
+        batch.close()
+        for op in ops:
+            op.close()
+
+
+def test_batch_kpoint_parity_and_time_reversal():
+    """One k-point task against the oracle's filter; and with B = 0 the Ritz
+    values after a batched filter + CholGS + RR satisfy eps(k) = eps(-k)
+    for the +-k pairs of the grid (time reversal)."""
+    from paper_2410_02754_amd import Batch
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        kg, _ = _systems(bmag=0.0)
+        op = _op(kg, stream)
+        tasks = []
+        X0 = synth.random_block(5, kg.n_dof, kg.n_vec)
+        for ik in range(8):
+            X = torch.tensor(X0, device="cuda")
+            tasks.append((op, ik, X, torch.empty_like(X)))
+        H3 = ham.build(kg, synth.veff, synth.bxc, ik=3)[1]
+        lam = np.linalg.eigvalsh(H3.toarray())
+        a, b, a0 = float(lam[60]), float(lam[-1] + 1.0), float(lam[0] - 0.2)
+        batch = Batch(tasks, 8)
+        batch.filter(a, b, a0)
+        torch.cuda.synchronize()
+        ref = och.cheb_filter(H3, X0, 8, a, b, a0)
+        err = np.abs(tasks[3][2].cpu().numpy() - ref).max() / np.abs(ref).max()
+        print(f"[batch k parity] rel err {err:.2e}", flush=True)
+        assert err < 1e-11
+        th = []
+        for op_, ik, X, W in tasks:
+            op_.chol_gs(X)
+            t, _ = op_.rayleigh_ritz(X, W, ik=ik)
+            th.append(t)
+        k = kg.kpts
+        for i in range(8):
+            j = int(np.argmin(np.linalg.norm(k + k[i], axis=1)))
+            d = np.abs(th[i][:20] - th[j][:20]).max()
+            assert d < 1e-9, (i, j, d)
+        batch.close()
+        op.close()
