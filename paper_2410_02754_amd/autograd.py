@@ -4,14 +4,22 @@ points.  Forward and backward both run in the library (the backward is the
 hand-written adjoint of chfsi_apply_H / chfsi_cheb_filter)."""
 from __future__ import annotations
 
+import weakref
+
 import torch
 
 
 def _ensure_fields(op, V, B):
-    key = (V.data_ptr(), V._version, B.data_ptr(), B._version)
-    if getattr(op, "_field_key", None) != key:
-        op.set_local(V.detach().contiguous(), B.detach().contiguous())
-        op._field_key = key
+    """Rebuild the cell operators unless they were built from these very
+    tensor objects, unmodified since (a freed temporary's address can be
+    reused, so identity is tracked with weak references, not pointers)."""
+    prev = getattr(op, "_field_src", None)
+    if prev is not None:
+        rv, vv, rb, vb = prev
+        if rv() is V and rb() is B and V._version == vv and B._version == vb:
+            return
+    op.set_local(V.detach().contiguous(), B.detach().contiguous())
+    op._field_src = (weakref.ref(V), V._version, weakref.ref(B), B._version)
 
 
 class ApplyH(torch.autograd.Function):

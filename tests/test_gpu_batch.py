@@ -99,8 +99,15 @@ def test_batch_kpoint_parity_and_time_reversal():
         op = _op(kg, stream)
         tasks = []
         X0 = synth.random_block(5, kg.n_dof, kg.n_vec)
+        # time reversal Theta = i sigma_y K: (u_up, u_dn) -> (conj(u_dn), -conj(u_up));
+        # the -k task starts from Theta X0 so the two filtered subspaces are Theta-related
+        TX0 = np.empty_like(X0)
+        TX0[0::2] = np.conj(X0[1::2])
+        TX0[1::2] = -np.conj(X0[0::2])
+        k = kg.kpts
         for ik in range(8):
-            X = torch.tensor(X0, device="cuda")
+            j = int(np.argmin(np.linalg.norm(k + k[ik], axis=1)))
+            X = torch.tensor(X0 if ik < j else TX0, device="cuda")
             tasks.append((op, ik, X, torch.empty_like(X)))
         H3 = ham.build(kg, synth.veff, synth.bxc, ik=3)[1]
         lam = np.linalg.eigvalsh(H3.toarray())
@@ -108,7 +115,8 @@ def test_batch_kpoint_parity_and_time_reversal():
         batch = Batch(tasks, 8)
         batch.filter(a, b, a0)
         torch.cuda.synchronize()
-        ref = och.cheb_filter(H3, X0, 8, a, b, a0)
+        j3 = int(np.argmin(np.linalg.norm(kg.kpts + kg.kpts[3], axis=1)))
+        ref = och.cheb_filter(H3, X0 if 3 < j3 else TX0, 8, a, b, a0)
         err = np.abs(tasks[3][2].cpu().numpy() - ref).max() / np.abs(ref).max()
         print(f"[batch k parity] rel err {err:.2e}", flush=True)
         assert err < 1e-11
@@ -117,7 +125,6 @@ def test_batch_kpoint_parity_and_time_reversal():
             op_.chol_gs(X)
             t, _ = op_.rayleigh_ritz(X, W, ik=ik)
             th.append(t)
-        k = kg.kpts
         for i in range(8):
             j = int(np.argmin(np.linalg.norm(k + k[i], axis=1)))
             d = np.abs(th[i][:20] - th[j][:20]).max()
