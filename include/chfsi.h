@@ -145,6 +145,28 @@ int chfsi_apply_H(chfsi_ctx* ctx, int ik, const void* X_d, int64_t ldx, void* Y_
 int chfsi_cheb_filter(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
                       int n_vec, int degree, double a, double b, double a0, int prec_mode);
 
+/* Ritz residuals in place: W_d[:, i] <- W_d[:, i] - theta_h[i] X_d[:, i] for
+ * i < n_vec.  After chfsi_rayleigh_ritz with resid_h non-NULL, work_d holds
+ * H_hat X for the rotated X, so this turns it into R = H_hat X - X diag(theta). */
+int chfsi_ritz_residual(chfsi_ctx* ctx, const void* X_d, int64_t ldx, void* W_d, int64_t ldw, int n_vec,
+                        const double* theta_h);
+
+/* Residual form of the filter (Sec. III.B.2: the Hamiltonian-times-residual
+ * reformulation that allows lower-precision products near convergence).  X_d
+ * holds Ritz vectors with Ritz values theta_h (host) and residuals R_d
+ * (= H_hat X - X diag(theta), from chfsi_ritz_residual).  With p_k the scaled
+ * Chebyshev polynomials of chfsi_cheb_filter, Y_k = X p_k(Theta) + Z_k where
+ *   Z_0 = 0, Z_1 = alpha_1 R,
+ *   Z_{k+1} = alpha_{k+1} (H_hat - c) Z_k + beta_{k+1} Z_{k-1} + alpha_{k+1} R p_k(Theta),
+ * so only the correction Z passes through operator products.  On return X_d
+ * holds Y_m = p_m(H_hat) X (the same result as chfsi_cheb_filter).  prec_mode
+ * CHFSI_PREC_MIXED runs every product H_hat Z_k in FP32 (Z is small when the
+ * residuals are); the recurrence and the final combination are FP64.
+ * work_d [2M][ldw] with ldw >= 2 n_vec (two Z blocks side by side). */
+int chfsi_cheb_filter_resid(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, const void* R_d, int64_t ldr,
+                            const double* theta_h, void* work_d, int64_t ldw, int n_vec, int degree, double a,
+                            double b, double a0, int prec_mode);
+
 /* Cholesky-Gram-Schmidt: S = X^H X (FP64), S = L L^H, X <- X L^{-H}, so that
  * the columns become orthonormal with the same span (the orthonormalisation
  * before the Rayleigh-Ritz step, Sec. III.B.2).  On CHFSI_ENOTPD *bad_col (if

@@ -16,7 +16,7 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_last_error", "chfsi_version", "chfsi_stats_enable", "chfsi_stats_read",
             "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
             "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
-            "chfsi_batch_destroy", "chfsi_batch_last_error"]
+            "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -81,6 +81,8 @@ def load():
         "chfsi_lanczos_bounds": ([vp, i32, i32, vp, pd, pd], i32),
         "chfsi_fill_random": ([vp, vp, i64, i32, i64, C.c_uint64, i64, i32, i64], i32),
         "chfsi_sync": ([vp], i32),
+        "chfsi_ritz_residual": ([vp, vp, i64, vp, i64, i32, pd], i32),
+        "chfsi_cheb_filter_resid": ([vp, i32, vp, i64, vp, i64, pd, vp, i64, i32, i32, dbl, dbl, dbl, i32], i32),
         "chfsi_batch_create": ([i32, C.POINTER(BatchTask), i32, i32, i32, C.POINTER(vp)], i32),
         "chfsi_batch_filter": ([vp, pd, pd, pd], i32),
         "chfsi_batch_tiles": ([vp, C.POINTER(i32), pd], i32),

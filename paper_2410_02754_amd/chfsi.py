@@ -137,6 +137,31 @@ class Operator:
                                              _PREC[prec]))
         return X
 
+    def ritz_residual(self, X, W, theta):
+        """W <- W - X diag(theta) (R = H X - X Theta when W = H X)."""
+        px, ldx, n = _block(X, "X")
+        pw, ldw, nw = _block(W, "W")
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if nw != n or th.size < n:
+            raise ValueError("W and theta must match X")
+        self._chk(self.lib.chfsi_ritz_residual(self.ctx, C.c_void_p(px), ldx, C.c_void_p(pw), ldw, n,
+                                               th.ctypes.data_as(C.POINTER(C.c_double))))
+        return W
+
+    def cheb_filter_resid(self, X, R, theta, work, degree: int, a: float, b: float, a0: float,
+                          ik: int = 0, prec="fp64"):
+        """Residual form of the filter; work must be [2M][>= 2 n_vec]."""
+        px, ldx, n = _block(X, "X")
+        pr, ldr, nr = _block(R, "R")
+        pw, ldw, nw = _block(work, "work")
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if nr != n or nw < 2 * n or th.size < n:
+            raise ValueError("R must match X, work must be [2M][>= 2 n_vec]")
+        self._chk(self.lib.chfsi_cheb_filter_resid(self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(pr), ldr,
+                                                   th.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(pw), ldw,
+                                                   n, int(degree), float(a), float(b), float(a0), _PREC[prec]))
+        return X
+
     def chol_gs(self, X):
         px, ldx, n = _block(X, "X")
         bad = C.c_int(-1)

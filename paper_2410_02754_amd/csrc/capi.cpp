@@ -255,6 +255,85 @@ int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, in
   API_END(c)
 }
 
+int chfsi_ritz_residual(chfsi_ctx* c, const void* X, int64_t ldx, void* W, int64_t ldw, int n_vec,
+                        const double* theta) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, W, ldw, n_vec, "W");
+  CHFSI_CHECK(theta != nullptr, CHFSI_EINVAL, "theta_h must be non-NULL");
+  std::vector<double> ab(2 * (size_t)n_vec);
+  for (int i = 0; i < n_vec; ++i) {
+    ab[i] = 1.0;
+    ab[n_vec + i] = -theta[i];
+  }
+  DevBuf<double> d;
+  d.upload(ab.data(), ab.size(), c->stream);
+  launch_cols_axpby(c, (double2*)W, ldw, (const double2*)X, ldx, 2 * c->n_nodes, n_vec, d.ptr, d.ptr + n_vec);
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  API_END(c)
+}
+
+int chfsi_cheb_filter_resid(chfsi_ctx* c, int ik, void* X, int64_t ldx, const void* R, int64_t ldr,
+                            const double* theta, void* work, int64_t ldw, int n_vec, int degree, double a, double b,
+                            double a0, int prec_mode) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  require_operator(c);
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, R, ldr, n_vec, "R");
+  CHFSI_CHECK(work != nullptr && ldw >= 2 * (int64_t)n_vec && ((uintptr_t)work % 16) == 0, CHFSI_EINVAL,
+              "work must be [2M][>= 2 n_vec], 16-byte aligned");
+  CHFSI_CHECK(theta != nullptr, CHFSI_EINVAL, "theta_h must be non-NULL");
+  CHFSI_CHECK(degree >= 1, CHFSI_EINVAL, "degree must be >= 1");
+  CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
+              "filter bounds must satisfy a0 < a < b");
+  CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
+  KPoint& kp = kpoint(c, ik);
+  const int m = degree, n = n_vec;
+  const int64_t rows = 2 * c->n_nodes;
+  const double e = 0.5 * (b - a), cc = 0.5 * (b + a), s1 = e / (a0 - cc);
+  std::vector<double> al(m + 1, 0.0), be(m + 1, 0.0);
+  double sg = s1;
+  al[1] = s1 / e;
+  for (int k = 2; k <= m; ++k) {
+    const double sn = 1.0 / (2.0 / s1 - sg);
+    al[k] = 2.0 * sn / e;
+    be[k] = -sg * sn;
+    sg = sn;
+  }
+  // scalar recurrences p_k(theta_i), k = 0..m; table of source scales
+  // src[k][i] = al[k] p_{k-1}(theta_i) for k = 2..m, and the final p_m
+  std::vector<double> tab((size_t)(m + 2) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double pkm1 = 1.0, pk = al[1] * (theta[i] - cc);   // p_0, p_1
+    for (int k = 2; k <= m; ++k) {
+      tab[(size_t)k * n + i] = al[k] * pk;              // al_k p_{k-1}
+      const double pn = al[k] * (theta[i] - cc) * pk + be[k] * pkm1;
+      pkm1 = pk;
+      pk = pn;
+    }
+    tab[(size_t)(m + 1) * n + i] = (m >= 1) ? pk : 1.0;  // p_m(theta_i)
+    tab[i] = 1.0;                                        // ones for the final combination
+  }
+  DevBuf<double> dt;
+  dt.upload(tab.data(), tab.size(), c->stream);
+  double2* Z[2] = {(double2*)work, (double2*)work + n};
+  // Z_1 = al_1 R
+  launch_axpby_rows(c, Z[0], ldw, (const double2*)R, ldr, rows, n, 0.0, al[1]);
+  int cur = 0;
+  for (int k = 2; k <= m; ++k) {
+    // Z_k = al_k (H - c) Z_{k-1} + be_k Z_{k-2} + al_k R p_{k-1}(Theta), written over Z_{k-2}
+    apply_H3(c, kp, Z[cur], ldw, Z[cur ^ 1], ldw, Z[cur ^ 1], ldw, n, prec_mode, al[k], k == 2 ? 0.0 : be[k],
+             -cc * al[k], (const double2*)R, ldr, dt.ptr + (size_t)k * n);
+    cur ^= 1;
+  }
+  // X <- X p_m(Theta) + Z_m
+  launch_cols_axpby(c, (double2*)X, ldx, Z[cur], ldw, rows, n, dt.ptr + (size_t)(m + 1) * n, dt.ptr);
+  CHFSI_HIP(hipStreamSynchronize(c->stream));   // dt leaves scope
+  API_END(c)
+}
+
 int chfsi_chol_gs(chfsi_ctx* c, void* X, int64_t ldx, int n_vec, int* bad_col) {
   if (!c) return CHFSI_EINVAL;
   API_BEGIN(c)

@@ -219,6 +219,13 @@ void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W
 void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
               const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta,
               double gamma);
+// ... + the column-scaled source sum_n rscale[n] Rs[:, n] (Rs may be null)
+void apply_H3(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+              const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta, double gamma,
+              const double2* Rs, int64_t ldr, const double* rscale);
+// Y[r][n] = a[n] Y[r][n] + b[n] X[r][n] with device per-column scalars
+void launch_cols_axpby(chfsi_ctx* c, double2* Y, int64_t ldy, const double2* X, int64_t ldx, int64_t rows,
+                       int n_vec, const double* a_d, const double* b_d);
 // dV[e][q] += alpha w_q J Re sum_n l^H y, dB_d[e][q] += alpha w_q J Re sum_n l^H sigma_d y
 void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
                    double alpha, double* dV, double* dB);

@@ -630,7 +630,8 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
     const int32_t* __restrict__ nlist_entry, const int32_t* __restrict__ nlist_atom,
     const int32_t* __restrict__ atom_npj, int max_pj, const typename C2<T>::type* __restrict__ Cp,
     int has_nl, const double2* __restrict__ X, int64_t ldx, double2* W, int64_t ldw,
-    const double2* Wold, int64_t ldo, int64_t n_nodes, int n_vec, double beta, double gamma) {
+    const double2* Wold, int64_t ldo, const double2* __restrict__ Rs, int64_t ldr,
+    const double* __restrict__ rscale, int64_t n_nodes, int n_vec, double beta, double gamma) {
   typedef typename C2<T>::type CT;
   const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t node = __builtin_amdgcn_readfirstlane((int)wid);
@@ -656,6 +657,12 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
           v.x += gamma * xv.x;
           v.y += gamma * xv.y;
         }
+        if (Rs) {
+          const double2 rv = Rs[r * ldr + col];
+          const double sc = rscale[col];
+          v.x += sc * rv.x;
+          v.y += sc * rv.y;
+        }
       }
       w[h][sp] = v;
     }
@@ -671,17 +678,26 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
     for (int t = l0; t < l1; ++t) {
       const int ent = nlist_entry[t], a = nlist_atom[t];
       const int npj = atom_npj[a];
-      for (int x = 0; x < npj; ++x) {
-        const CT p = proj[(size_t)ent * max_pj + x];
+      CT p[kMaxPj];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int col = c0 + 64 * h;
-          if (col >= n_vec) continue;
+      for (int x = 0; x < kMaxPj; ++x) {
+        p[x].x = (T)0;
+        p[x].y = (T)0;
+        if (x < npj) p[x] = proj[(size_t)ent * max_pj + x];
+      }
+      // all coefficient loads of this (entry, atom) are independent
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = c0 + 64 * h;
+        if (col >= n_vec) continue;
+#pragma unroll
+        for (int x = 0; x < kMaxPj; ++x) {
+          if (x >= npj) continue;
 #pragma unroll
           for (int sp = 0; sp < 2; ++sp) {
             const CT cv = Cp[((size_t)a * mr + 2 * x + sp) * n_vec + col];
-            acc[h][sp][0] += p.x * cv.x - p.y * cv.y;
-            acc[h][sp][1] += p.x * cv.y + p.y * cv.x;
+            acc[h][sp][0] += p[x].x * cv.x - p[x].y * cv.y;
+            acc[h][sp][1] += p[x].x * cv.y + p[x].y * cv.x;
           }
         }
       }
@@ -744,7 +760,8 @@ template <class T>
 static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<T>::type* proj,
                                  const typename C2<T>::type* Cp, const double2* X, int64_t ldx,
                                  double2* W, int64_t ldw, const double2* Wold, int64_t ldo, int n_vec,
-                                 double beta, double gamma) {
+                                 double beta, double gamma, const double2* Rs = nullptr, int64_t ldr = 0,
+                                 const double* rscale = nullptr) {
   const int64_t rows = 2 * c->n_nodes;
   StageTimer tm(c, CHFSI_STAGE_AXPY, Cp ? 8.0 * 2.0 * nl.n_entries * nl.max_pj * n_vec : 0.0, 0.0,
                 (double)rows * n_vec * sizeof(double2) * (1.0 + (beta != 0.0) + (gamma != 0.0)));
@@ -753,30 +770,59 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
   hipLaunchKernelGGL(init_nl_kernel<T>, grid, dim3(256), 0, c->stream, proj,
                      has ? nl.node_off.ptr : nullptr, has ? nl.nlist_entry.ptr : nullptr,
                      has ? nl.nlist_atom.ptr : nullptr, has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has,
-                     X, ldx, W, ldw, Wold, ldo, c->n_nodes, n_vec, beta, gamma);
+                     X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale, c->n_nodes, n_vec, beta, gamma);
   LAUNCH_CHECK();
 }
 
-void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-              const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta,
-              double gamma) {
+void apply_H3(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+              const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta, double gamma,
+              const double2* Rs, int64_t ldr, const double* rscale) {
   if (prec == CHFSI_PREC_MIXED) {
     const float2* Cp = nonlocal_coeffs<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, n_vec, alpha);
-    init_and_backproduct<float>(c, kp.nl, kp.nl.proj32.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta,
-                                gamma);
+    init_and_backproduct<float>(c, kp.nl, kp.nl.proj32.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta, gamma,
+                                Rs, ldr, rscale);
     if (kp.gamma)
       launch_cells_cb<float, false>(c, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
     else
       launch_cells_cb<float, true>(c, kp.cell32.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
   } else {
     const double2* Cp = nonlocal_coeffs<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, n_vec, alpha);
-    init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta,
-                                 gamma);
+    init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta, gamma,
+                                 Rs, ldr, rscale);
     if (kp.gamma)
       launch_cells_cb<double, false>(c, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
     else
       launch_cells_cb<double, true>(c, kp.cell64.ptr, kp.nmat, X, ldx, W, ldw, n_vec, alpha);
   }
+}
+
+void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+              const double2* Wold, int64_t ldo, int n_vec, int prec, double alpha, double beta,
+              double gamma) {
+  apply_H3(c, kp, X, ldx, W, ldw, Wold, ldo, n_vec, prec, alpha, beta, gamma, nullptr, 0, nullptr);
+}
+
+// Y[r][n] = a[n] Y[r][n] + b[n] X[r][n]   (per-column scalars on the device)
+__global__ void cols_axpby_kernel(double2* __restrict__ Y, int64_t ldy, const double2* __restrict__ X, int64_t ldx,
+                                  int64_t rows, int n_vec, const double* __restrict__ a, const double* __restrict__ b) {
+  const int64_t total = rows * n_vec;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / n_vec;
+    const int n = (int)(t - r * n_vec);
+    const double2 y = Y[r * ldy + n], x = X[r * ldx + n];
+    Y[r * ldy + n] = double2{a[n] * y.x + b[n] * x.x, a[n] * y.y + b[n] * x.y};
+  }
+}
+
+void launch_cols_axpby(chfsi_ctx* c, double2* Y, int64_t ldy, const double2* X, int64_t ldx, int64_t rows,
+                       int n_vec, const double* a_d, const double* b_d) {
+  const int64_t total = rows * n_vec;
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, 3.0 * (double)total * sizeof(double2));
+  hipLaunchKernelGGL(cols_axpby_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, c->stream, Y, ldy, X, ldx, rows,
+                     n_vec, a_d, b_d);
+  LAUNCH_CHECK();
 }
 
 void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
