@@ -176,8 +176,10 @@ int chfsi_chol_gs(chfsi_ctx* ctx, void* X_d, int64_t ldx, int n_vec, int* bad_co
 
 /* Rayleigh-Ritz on an orthonormal block (Sec. III.B.2): W = H_hat^k X,
  * H_p = X^H W, H_p = Q diag(theta) Q^H (ascending), X <- X Q.  ritz_h[n_vec]
- * receives theta; if resid_h is non-NULL it receives ||H_hat x_i - theta_i x_i||.
- * work_d [2M][ldw] (ldw >= n_vec) is overwritten.  FP64 throughout. */
+ * receives theta; if resid_h is non-NULL it receives ||H_hat x_i - theta_i x_i||
+ * and work_d holds H_hat X for the rotated X on return (the input of
+ * chfsi_ritz_residual).  work_d [2M][ldw] (ldw >= n_vec) is overwritten.  FP64
+ * throughout. */
 int chfsi_rayleigh_ritz(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
                         int n_vec, double* ritz_h, double* resid_h);
 
