@@ -14,9 +14,11 @@ Printed JSON (one line, rank 0):
   ms_per_step  wall time per FP64 pass (filter + CholGS + RR), the K timed passes
   roofline     the FP64 cell-product kernel (dominant): algorithmic flops per
                launch / mean launch time from HIP events, against 78.6 TFLOP/s
-  mixed        the same passes with FP32 cell/projector products (applies
-               1..m-1), from the same start: per-pass time, speedup and the
-               largest Ritz-value difference from the FP64 run
+  mixed        from the same FP64 prologue and warm-up, the timed passes with FP32
+               cell/projector products in applies 1..m-1: per-pass time, speedup and
+               the largest Ritz-value difference from the FP64 run
+  mixed_resid  the same with the residual form of the filter (every correction
+               product in FP32)
   cpu_baseline the FP64 oracle on a bounded sample (see `sample`)
 """
 from __future__ import annotations
@@ -227,9 +229,11 @@ def main():
 
     if not args.no_mixed:
         for key, resid_form in (("mixed", False), ("mixed_resid", True)):
+            # the same FP64 prologue and warm-up passes as the FP64 run (bitwise the
+            # same state: every kernel is deterministic); only the timed passes differ
             theta, _ = start(op, s, X, W, torch)
-            theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "mixed", torch,
-                                           key + " warmup", resid_form)
+            theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "fp64", torch,
+                                           key + " fp64 warmup")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             thetam, rm, mt, mft, mst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "mixed", torch, key,
