@@ -19,7 +19,10 @@ ARCH = os.environ.get("CHFSI_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-Wno-unused-command-line-argument"]
+          "-Wno-unused-command-line-argument",
+          # keep MFMA accumulators in VGPRs: the default heuristic shuffled them
+          # through AGPRs (v_accvgpr moves) inside the cell-product loop
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _hipcc():

@@ -192,11 +192,15 @@ __device__ __forceinline__ void cell_tile(CellSmem<T, CB>& sm, const T* __restri
   auto& sB = sm.sB;
   auto& sNode = sm.sNode;
   __syncthreads();                        // previous tile's LDS reads are done
+
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave & 1, wc = wave >> 1;
   const int rb = rt * 2 + wr;
   const bool row_active = rb < nrb;
+  // an inactive row block (odd nrb) computes on the last valid block and skips the epilogue,
+  // so the stage loop below has no branches and loads overlap the MFMAs
+  const int rb_eff = row_active ? rb : nrb - 1;
   const int col0 = ct * BN;
 
   for (int i = tid; i < nloc; i += 256) sNode[i] = cell_nodes[(size_t)e * nloc + i];
@@ -208,30 +212,40 @@ __device__ __forceinline__ void cell_tile(CellSmem<T, CB>& sm, const T* __restri
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[cb][k] = V4{0, 0, 0, 0};
 
-  const T* Abase = cm + ((size_t)(e * nrb + (row_active ? rb : 0)) * nkb) * nmat * 64 + lane;
+  const T* Abase = cm + ((size_t)(e * nrb + rb_eff) * nkb) * nmat * 64 + lane;
   const int nstage = nkb / 2;
   double2 pre[NPRE];
   T aC[2][NM], aN[2][NM];
 
+  // per-thread constants of the gather: (k node, spin, column) of each prefetch slot
+  int g_kk[NPRE], g_sp[NPRE], g_col[NPRE];
+  bool g_cv[NPRE];
+#pragma unroll
+  for (int j = 0; j < NPRE; ++j) {
+    const int idx = tid + 256 * j;
+    g_col[j] = idx % BN;
+    g_sp[j] = (idx / BN) & 1;
+    g_kk[j] = idx / (2 * BN);
+    g_cv[j] = col0 + g_col[j] < n_vec;
+  }
+  const int gcol_max = n_vec - 1;
+
   auto gload = [&](int s) {
 #pragma unroll
     for (int j = 0; j < NPRE; ++j) {
-      const int idx = tid + 256 * j;
-      const int col = idx % BN, sp = (idx / BN) & 1, kk = idx / (2 * BN);
-      const int knode = s * BK + kk;
-      const int gcol = col0 + col;
-      double2 v = {0.0, 0.0};
-      if (knode < nloc && gcol < n_vec) v = X[(2 * (int64_t)sNode[knode] + sp) * ldx + gcol];
-      pre[j] = v;
+      const int knode = s * BK + g_kk[j];
+      const bool valid = g_cv[j] && knode < nloc;
+      const int kn = knode < nloc ? knode : 0;                    // in-bounds address always
+      const int gcol = min(col0 + g_col[j], gcol_max);
+      const double2 v = X[(2 * (int64_t)sNode[kn] + g_sp[j]) * ldx + gcol];
+      pre[j] = valid ? v : double2{0.0, 0.0};
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < NPRE; ++j) {
-      const int idx = tid + 256 * j;
-      const int col = idx % BN, sp = (idx / BN) & 1, kk = idx / (2 * BN);
-      sB[buf][2 * sp][kk][col] = (T)pre[j].x;
-      sB[buf][2 * sp + 1][kk][col] = (T)pre[j].y;
+      sB[buf][2 * g_sp[j]][g_kk[j]][g_col[j]] = (T)pre[j].x;
+      sB[buf][2 * g_sp[j] + 1][g_kk[j]][g_col[j]] = (T)pre[j].y;
     }
   };
   auto aload = [&](int s, T (&dst)[2][NM]) {
@@ -243,65 +257,62 @@ __device__ __forceinline__ void cell_tile(CellSmem<T, CB>& sm, const T* __restri
     }
   };
 
-  if (row_active) aload(0, aC);
+  aload(0, aC);
   gload(0);
   lstore(0);
   __syncthreads();
   for (int s = 0; s < nstage; ++s) {
     const int buf = s & 1;
-    if (s + 1 < nstage) {
-      gload(s + 1);
-      if (row_active) aload(s + 1, aN);
-    }
-    if (row_active) {
+    const int sn = s + 1 < nstage ? s + 1 : s;      // the last stage reloads itself (unused)
+    gload(sn);
+    aload(sn, aN);
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        const T hp = aC[kk][0], hm = aC[kk][1], bx = aC[kk][2], by = aC[kk][3];
-        const T sv = HAS_S ? aC[kk][NM - 1] : (T)0;
-        const T nby = -by, nsv = -sv;
-        const int krow = kk * 4 + (lane >> 4);
-        T ba[CB], bb[CB], bc[CB], bd[CB];
+    for (int kk = 0; kk < 2; ++kk) {
+      const T hp = aC[kk][0], hm = aC[kk][1], bx = aC[kk][2], by = aC[kk][3];
+      const T sv = HAS_S ? aC[kk][NM - 1] : (T)0;
+      const T nby = -by, nsv = -sv;
+      const int krow = kk * 4 + (lane >> 4);
+      T ba[CB], bb[CB], bc[CB], bd[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int col = wc * (CB * 16) + cb * 16 + (lane & 15);
+        ba[cb] = sB[buf][0][krow][col];
+        bb[cb] = sB[buf][1][krow][col];
+        bc[cb] = sB[buf][2][krow][col];
+        bd[cb] = sB[buf][3][krow][col];
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[cb][0] = mfma(hp, ba[cb], acc[cb][0]);
+        acc[cb][1] = mfma(hp, bb[cb], acc[cb][1]);
+        acc[cb][2] = mfma(hm, bc[cb], acc[cb][2]);
+        acc[cb][3] = mfma(hm, bd[cb], acc[cb][3]);
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[cb][0] = mfma(bx, bc[cb], acc[cb][0]);
+        acc[cb][1] = mfma(bx, bd[cb], acc[cb][1]);
+        acc[cb][2] = mfma(bx, ba[cb], acc[cb][2]);
+        acc[cb][3] = mfma(bx, bb[cb], acc[cb][3]);
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[cb][0] = mfma(by, bd[cb], acc[cb][0]);
+        acc[cb][1] = mfma(nby, bc[cb], acc[cb][1]);
+        acc[cb][2] = mfma(nby, bb[cb], acc[cb][2]);
+        acc[cb][3] = mfma(by, ba[cb], acc[cb][3]);
+      }
+      if (HAS_S) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-          const int col = wc * (CB * 16) + cb * 16 + (lane & 15);
-          ba[cb] = sB[buf][0][krow][col];
-          bb[cb] = sB[buf][1][krow][col];
-          bc[cb] = sB[buf][2][krow][col];
-          bd[cb] = sB[buf][3][krow][col];
-        }
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          acc[cb][0] = mfma(hp, ba[cb], acc[cb][0]);
-          acc[cb][1] = mfma(hp, bb[cb], acc[cb][1]);
-          acc[cb][2] = mfma(hm, bc[cb], acc[cb][2]);
-          acc[cb][3] = mfma(hm, bd[cb], acc[cb][3]);
-        }
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          acc[cb][0] = mfma(bx, bc[cb], acc[cb][0]);
-          acc[cb][1] = mfma(bx, bd[cb], acc[cb][1]);
-          acc[cb][2] = mfma(bx, ba[cb], acc[cb][2]);
-          acc[cb][3] = mfma(bx, bb[cb], acc[cb][3]);
-        }
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          acc[cb][0] = mfma(by, bd[cb], acc[cb][0]);
-          acc[cb][1] = mfma(nby, bc[cb], acc[cb][1]);
-          acc[cb][2] = mfma(nby, bb[cb], acc[cb][2]);
-          acc[cb][3] = mfma(by, ba[cb], acc[cb][3]);
-        }
-        if (HAS_S) {
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            acc[cb][0] = mfma(nsv, bb[cb], acc[cb][0]);
-            acc[cb][1] = mfma(sv, ba[cb], acc[cb][1]);
-            acc[cb][2] = mfma(nsv, bd[cb], acc[cb][2]);
-            acc[cb][3] = mfma(sv, bc[cb], acc[cb][3]);
-          }
+          acc[cb][0] = mfma(nsv, bb[cb], acc[cb][0]);
+          acc[cb][1] = mfma(sv, ba[cb], acc[cb][1]);
+          acc[cb][2] = mfma(nsv, bd[cb], acc[cb][2]);
+          acc[cb][3] = mfma(sv, bc[cb], acc[cb][3]);
         }
       }
     }
-    if (s + 1 < nstage) lstore(buf ^ 1);
+    lstore(buf ^ 1);       // the other buffer was last read before the previous barrier
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
@@ -332,7 +343,6 @@ __device__ __forceinline__ void cell_tile(CellSmem<T, CB>& sm, const T* __restri
     }
   }
 }
-
 
 template <class T, int CB, bool HAS_S>
 __global__ __launch_bounds__(256) void cell_apply_kernel(
