@@ -36,6 +36,35 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6     # TFLOP/s, MI355X dense FP64 (vector = matrix)
 PEAK_FP32 = 157.3    # TFLOP/s, MI355X dense FP32 matrix
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cell_apply_fp64_scale_traffic.md")
+
+
+def cell_kernel_fingerprint():
+    """sha256 over the cell-kernel sources and the device compile flags: a
+    counter record taken for another build of the kernel does not apply."""
+    import hashlib
+    from paper_2410_02754_amd import build as b
+    h = hashlib.sha256()
+    for f in ("cell.hip", "mfma.h"):
+        with open(os.path.join(ROOT, "paper_2410_02754_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(b.COMMON).encode())
+    return h.hexdigest()
+
+
+def measured_traffic(grid_wg):
+    """HBM bytes per filter launch of the FP64 cell kernel from the committed
+    counter record (calibrated FETCH_SIZE + WRITE_SIZE), or None when the record
+    is missing, was taken on another launch shape or for other kernel sources."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            line = next(l for l in fh if l.startswith("traffic_record: "))
+        rec = json.loads(line[len("traffic_record: "):])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_sha256") != cell_kernel_fingerprint() or rec.get("grid_wg") != grid_wg:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def log(*a):
@@ -153,6 +182,16 @@ def cpu_baseline(s_name):
             "apply_s": t_apply}
 
 
+def cell_alg_bytes(s):
+    """Algorithmic HBM bytes of one filter launch (one colour, 128 columns):
+    the Gamma-point Pauli-form operator (4 real (p+1)^3 x (p+1)^3 FP64 matrices
+    per cell) read once, the cell's gathered input rows read once and its output
+    rows read and written once."""
+    n_colour_cells = int(np.prod(s.n_cells)) // 8
+    nloc = (s.p + 1) ** 3
+    return n_colour_cells * (4.0 * nloc * nloc * 8 + 3.0 * 2 * nloc * s.block * 16)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +241,11 @@ def main():
     cell_ms = fst["cell_ms"] / max(1, fst["cell_launches"])
     achieved = cell_per_launch / (cell_ms * 1e-3) / 1e12 if cell_ms > 0 else 0.0
     exec_tf = fst["cell_exec"] / (fst["cell_ms"] * 1e-3) / 1e12 if fst["cell_ms"] > 0 else 0.0
+    # filter launches: one colour of cells x row tiles x column tiles of 128
+    n_colour_cells = int(np.prod(s.n_cells)) // 8
+    nloc = (s.p + 1) ** 3
+    grid_wg = n_colour_cells * (((nloc + 15) // 16 + 1) // 2) * ((s.block + 127) // 128)
+    traffic = measured_traffic(grid_wg)
 
     out = {
         "metric": "ChFSI filter TFLOP/s + s per ChFSI pass; FP32 vs FP64 filter at 1e-7 Ha eigs",
@@ -217,7 +261,10 @@ def main():
         "s_per_pass": round(total / args.steps, 3),
         "filter_s_per_pass": round(sum(ftimes) / args.steps, 3),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_bytes_per_launch": cell_alg_bytes(s),
                      "kernel": "cell_apply_kernel<double> (gather + Pauli-form cell products + scatter-add)",
                      "flops_per_launch": cell_per_launch, "mean_launch_ms": round(cell_ms, 4),
                      "executed_mfma_tflops": round(exec_tf, 3),

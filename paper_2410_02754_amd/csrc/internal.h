@@ -211,6 +211,8 @@ void hermitian_eig(const std::vector<cplx>& A, int n, std::vector<double>& w, st
 void launch_cell_setup(chfsi_ctx* c, KPoint& kp, const double* V, const double* B,
                        const double* U0, const double* S);
 void launch_cell_to_f32(chfsi_ctx* c, KPoint& kp);
+void launch_cell_products(chfsi_ctx* c, KPoint& kp, int prec, const double2* X, int64_t ldx, double2* W,
+                          int64_t ldw, int n_vec, double alpha);
 int check_finite(chfsi_ctx* c, const double* p, int64_t n);
 // W <- alpha H_hat X + beta W + gamma X   (W is not read when beta == 0)
 void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
