@@ -492,6 +492,7 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
   nl.n_entries = 0;
   nl.max_pj = 1;
   nl.n_chunks = 0;
+  nl.n_pairs = 0;
   if (n_atoms == 0) return;
   std::vector<AtomWork> work(n_atoms);
   parallel_for(n_atoms, [&](int a) { atom_tables(c, kp.k, atoms[a], work[a]); });
@@ -528,30 +529,54 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
         delta[((size_t)a * 2 * mp + i) * 2 * mp + j] = double2{v.real(), v.imag()};
       }
   }
-  // chunks for the reduction C = P^H X
-  std::vector<int32_t> ch_atom, ch_b, ch_e, atom_chunk0(n_atoms + 1, 0);
+  // chunks for the reduction C = P^H X (support entries are sorted by node)
+  std::vector<int32_t> ch_atom, ch_b, ch_e, ch_win, atom_chunk0(n_atoms + 1, 0);
   for (int a = 0; a < n_atoms; ++a) {
     atom_chunk0[a] = (int32_t)ch_atom.size();
-    for (int s = atom_off[a]; s < atom_off[a + 1]; s += kNlChunk) {
+    for (int s = atom_off[a]; s < atom_off[a + 1];) {
+      const int win = sup[s] / kNlWindow;
+      int e = s;
+      while (e < atom_off[a + 1] && e - s < kNlChunk && sup[e] / kNlWindow == win) ++e;
       ch_atom.push_back(a);
       ch_b.push_back(s);
-      ch_e.push_back(std::min(s + kNlChunk, atom_off[a + 1]));
+      ch_e.push_back(e);
+      ch_win.push_back(win);
+      s = e;
     }
   }
   atom_chunk0[n_atoms] = (int32_t)ch_atom.size();
   nl.n_chunks = (int)ch_atom.size();
-  // node-centric lists for the back-product (deterministic, no atomics)
+  std::vector<int32_t> ch_order(nl.n_chunks);
+  for (int i = 0; i < nl.n_chunks; ++i) ch_order[i] = i;
+  std::stable_sort(ch_order.begin(), ch_order.end(), [&](int x, int y) {
+    return ch_win[x] != ch_win[y] ? ch_win[x] < ch_win[y] : ch_atom[x] < ch_atom[y];
+  });
+  // run lists for the back-product (deterministic, no atomics)
   std::vector<std::array<int32_t, 3>> trip(nl.n_entries);
   for (int a = 0; a < n_atoms; ++a)
     for (int s = atom_off[a]; s < atom_off[a + 1]; ++s) trip[s] = {sup[s], a, s};
   std::sort(trip.begin(), trip.end());
-  std::vector<int32_t> noff(c->n_nodes + 1, 0), nl_e(trip.size()), nl_a(trip.size());
-  for (size_t i = 0; i < trip.size(); ++i) {
-    noff[trip[i][0] + 1] += 1;
-    nl_a[i] = trip[i][1];
-    nl_e[i] = trip[i][2];
+  const int64_t n_runs = (c->n_nodes + kNlRun - 1) / kNlRun;
+  std::vector<int32_t> run_off(n_runs + 1, 0), pair_atom, pair_ent;
+  std::vector<int32_t> here;
+  size_t t = 0;
+  for (int64_t r = 0; r < n_runs; ++r) {
+    run_off[r] = (int32_t)pair_atom.size();
+    const int64_t node_end = std::min<int64_t>((r + 1) * kNlRun, c->n_nodes);
+    here.clear();
+    for (size_t u = t; u < trip.size() && trip[u][0] < node_end; ++u) here.push_back(trip[u][1]);
+    std::sort(here.begin(), here.end());
+    here.erase(std::unique(here.begin(), here.end()), here.end());
+    const size_t base = pair_atom.size();
+    pair_atom.insert(pair_atom.end(), here.begin(), here.end());
+    pair_ent.resize(pair_atom.size() * kNlRun, -1);
+    for (; t < trip.size() && trip[t][0] < node_end; ++t) {
+      const size_t k = std::lower_bound(here.begin(), here.end(), trip[t][1]) - here.begin();
+      pair_ent[(base + k) * kNlRun + (trip[t][0] - r * kNlRun)] = trip[t][2];
+    }
   }
-  for (int64_t i = 0; i < c->n_nodes; ++i) noff[i + 1] += noff[i];
+  run_off[n_runs] = (int32_t)pair_atom.size();
+  nl.n_pairs = (int64_t)pair_atom.size();
   hipStream_t s = c->stream;
   nl.sup_node.upload(sup.data(), sup.size(), s);
   nl.proj.upload(proj.data(), proj.size(), s);
@@ -562,10 +587,11 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
   nl.chunk_atom.upload(ch_atom.data(), ch_atom.size(), s);
   nl.chunk_begin.upload(ch_b.data(), ch_b.size(), s);
   nl.chunk_end.upload(ch_e.data(), ch_e.size(), s);
+  nl.chunk_order.upload(ch_order.data(), ch_order.size(), s);
   nl.atom_chunk0.upload(atom_chunk0.data(), atom_chunk0.size(), s);
-  nl.node_off.upload(noff.data(), noff.size(), s);
-  nl.nlist_entry.upload(nl_e.data(), nl_e.size(), s);
-  nl.nlist_atom.upload(nl_a.data(), nl_a.size(), s);
+  nl.run_off.upload(run_off.data(), run_off.size(), s);
+  nl.pair_atom.upload(pair_atom.data(), pair_atom.size(), s);
+  nl.pair_ent.upload(pair_ent.data(), pair_ent.size(), s);
   CHFSI_HIP(hipStreamSynchronize(s));   // host vectors go out of scope
 }
 

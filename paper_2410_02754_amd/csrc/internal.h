@@ -101,19 +101,27 @@ struct NonlocalK {
   DevBuf<double2> delta;        // [n_atoms][2 max_pj][2 max_pj]
   DevBuf<int32_t> atom_off;     // [n_atoms + 1] entry offsets
   DevBuf<int32_t> atom_npj;     // [n_atoms]
-  // chunked reduction work list for C = P^H X: chunks of kNlChunk entries
+  // chunked reduction work list for C = P^H X: the entries of one atom inside one
+  // window of kNlWindow consecutive global nodes (at most kNlChunk of them);
+  // chunk ids are grouped by atom (the reduction order), chunk_order lists them
+  // by (window, atom) so that chunks reading the same rows run together
   int n_chunks = 0;
   DevBuf<int32_t> chunk_atom;   // [n_chunks]
   DevBuf<int32_t> chunk_begin;  // [n_chunks]
   DevBuf<int32_t> chunk_end;    // [n_chunks]
+  DevBuf<int32_t> chunk_order;  // [n_chunks] launch order
   DevBuf<int32_t> atom_chunk0;  // [n_atoms + 1]
-  // node-centric back-product over every global node: the (entry, atom) pairs
-  // of node I are nlist_*[node_off[I] .. node_off[I+1])
-  DevBuf<int32_t> node_off;     // [n_nodes + 1]
-  DevBuf<int32_t> nlist_entry;  // [n_entries]
-  DevBuf<int32_t> nlist_atom;   // [n_entries]
+  // back-product over runs of kNlRun consecutive global nodes: the atoms whose
+  // support meets run r are pair_atom[run_off[r] .. run_off[r + 1]) (ascending),
+  // and pair_ent[pair][i] is that atom's support entry of node kNlRun r + i (-1: none)
+  int64_t n_pairs = 0;
+  DevBuf<int32_t> run_off;      // [n_runs + 1]
+  DevBuf<int32_t> pair_atom;    // [n_pairs]
+  DevBuf<int32_t> pair_ent;     // [n_pairs][kNlRun]
 };
-constexpr int kNlChunk = 256;
+constexpr int kNlChunk = 512;
+constexpr int kNlWindow = 1024;
+constexpr int kNlRun = 16;
 
 // ---------------------------------------------------------------- context
 struct KPoint {

@@ -89,74 +89,96 @@ template <> struct C2<float> { typedef float2 type; };
 
 constexpr int kMaxPj = 9;
 
-// Contraction partials, one wave per (chunk of an atom's support, 64-column
+// Contraction partials, one wave per (chunk of an atom's support, 32-column
 // tile): partial[chunk][2 chi + s][n] = sum_j conj(P[j][chi]) X[2 node_j + s][n].
-// Entries are processed four at a time so that eight independent row loads
-// are in flight per wave; the projector values are wave-uniform (scalar loads).
+// Done as 16x16x4 MFMAs: row = projector index chi (n_pj <= 9 of the 16 rows
+// used), k = four support entries per step, column = 16 of the tile's columns;
+// sixteen entries' operands are loaded before their MFMAs are issued.
 template <class T>
 __global__ __launch_bounds__(256) void nl_contract_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ sup_node,
     const int32_t* __restrict__ chunk_atom, const int32_t* __restrict__ chunk_begin,
-    const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ atom_npj, int max_pj,
-    int n_work, int n_coltiles, const double2* __restrict__ X, int64_t ldx, int n_vec,
-    typename C2<T>::type* __restrict__ partial) {
+    const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_order,
+    const int32_t* __restrict__ atom_npj, int max_pj, int n_work, int n_coltiles,
+    const double2* __restrict__ X, int64_t ldx, int n_vec, typename C2<T>::type* __restrict__ partial) {
   typedef typename C2<T>::type CT;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-  if (wid >= n_work) return;
+  typedef typename Vec4<T>::type V4;
+  constexpr int U = 4;                    // k-steps per batch
+  // each XCD takes a contiguous range of the (window, atom)-ordered chunks, so the
+  // chunks of different atoms over the same rows meet in that XCD's L2
+  const int per_xcd = (int)((gridDim.x + 7) / 8);
+  const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  const int wid = __builtin_amdgcn_readfirstlane(bid * 4 + (int)(threadIdx.x >> 6));
+  if (wid >= n_work) return;              // no barrier in this kernel
   const int lane = threadIdx.x & 63;
-  const int ch = wid / n_coltiles, ct = wid - ch * n_coltiles;
+  const int kl = lane >> 4, il = lane & 15;
+  const int oi = wid / n_coltiles, ct = wid - oi * n_coltiles;
+  const int ch = chunk_order[oi];
   const int a = chunk_atom[ch], b = chunk_begin[ch], e = chunk_end[ch];
   const int npj = atom_npj[a];
-  const int col = ct * 64 + lane;
-  const bool cv = col < n_vec;
-  T ar[2][kMaxPj], ai[2][kMaxPj];
+  const bool rv = il < npj;               // this lane's A row is a projector in use
+  int col[2];
+  bool cv[2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    col[cb] = ct * 32 + cb * 16 + il;
+    cv[cb] = col[cb] < n_vec;
+    if (!cv[cb]) col[cb] = n_vec - 1;     // clamped: loads stay in bounds
+  }
+  V4 cr[2][2], ci[2][2];                  // [spin][16-column block]
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int x = 0; x < kMaxPj; ++x) ar[sp][x] = ai[sp][x] = (T)0;
-  auto accum = [&](int j, const double2& x0, const double2& x1) {
-    const T xr[2] = {(T)x0.x, (T)x1.x}, xi[2] = {(T)x0.y, (T)x1.y};
+    for (int cb = 0; cb < 2; ++cb) cr[sp][cb] = ci[sp][cb] = V4{0, 0, 0, 0};
+  for (int j0 = b; j0 < e; j0 += 4 * U) {
+    CT pv[U];
+    double2 xv[U][2][2];
 #pragma unroll
-    for (int x = 0; x < kMaxPj; ++x) {
-      if (x < npj) {
-        const CT p = proj[(size_t)j * max_pj + x];
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + 4 * u + kl;      // entry of this lane's k index
+      const bool jv = j < e;
+      const int64_t nd = sup_node[jv ? j : b];
+      pv[u] = (jv && rv) ? proj[(size_t)j * max_pj + il] : CT{(T)0, (T)0};
 #pragma unroll
-        for (int sp = 0; sp < 2; ++sp) {
-          ar[sp][x] += p.x * xr[sp] + p.y * xi[sp];     // conj(p) * x
-          ai[sp][x] += p.x * xi[sp] - p.y * xr[sp];
+      for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const double2 v = X[(2 * nd + sp) * ldx + col[cb]];
+          xv[u][sp][cb] = (jv && cv[cb]) ? v : double2{0.0, 0.0};
         }
-      }
-    }
-  };
-  int j = b;
-  for (; j + 3 < e; j += 4) {
-    double2 x[4][2];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t r = 2 * (int64_t)sup_node[j + u];
-      x[u][0] = cv ? X[r * ldx + col] : double2{0.0, 0.0};
-      x[u][1] = cv ? X[(r + 1) * ldx + col] : double2{0.0, 0.0};
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) accum(j + u, x[u][0], x[u][1]);
-  }
-  for (; j < e; ++j) {
-    const int64_t r = 2 * (int64_t)sup_node[j];
-    const double2 x0 = cv ? X[r * ldx + col] : double2{0.0, 0.0};
-    const double2 x1 = cv ? X[(r + 1) * ldx + col] : double2{0.0, 0.0};
-    accum(j, x0, x1);
-  }
-  if (!cv) return;
+    for (int u = 0; u < U; ++u) {
+      const T pr = pv[u].x, pi = pv[u].y, npi = -pv[u].y;
 #pragma unroll
-  for (int x = 0; x < kMaxPj; ++x)
-    if (x < max_pj)
+      for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const T xr = (T)xv[u][sp][cb].x, xi = (T)xv[u][sp][cb].y;
+          cr[sp][cb] = mfma(pr, xr, cr[sp][cb]);      // conj(p) x
+          cr[sp][cb] = mfma(pi, xi, cr[sp][cb]);
+          ci[sp][cb] = mfma(pr, xi, ci[sp][cb]);
+          ci[sp][cb] = mfma(npi, xr, ci[sp][cb]);
+        }
+    }
+  }
+  CT* out = partial + (size_t)ch * 2 * max_pj * n_vec;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int x = acc_row<T>(lane, j);
+    if (x >= npj) continue;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      if (!cv[cb]) continue;
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) {
         CT v;
-        v.x = ar[sp][x];
-        v.y = ai[sp][x];
-        partial[((size_t)ch * 2 * max_pj + 2 * x + sp) * n_vec + col] = v;
+        v.x = cr[sp][cb][j];
+        v.y = ci[sp][cb][j];
+        out[(size_t)(2 * x + sp) * n_vec + col[cb]] = v;
       }
+    }
+  }
 }
 
 // Csum[a][r][n] = sum over the chunks of atom a of partial[chunk][r][n] (chunk order fixed)
@@ -233,102 +255,117 @@ __global__ __launch_bounds__(64) void nl_delta_kernel(const typename C2<T>::type
 }
 
 // Recurrence initialisation fused with the nonlocal back-product, one wave per
-// (node, 128-column tile), two columns per lane:
-//   W[2I+s][n] = beta W[2I+s][n] + gamma X[2I+s][n]
-//               + sum_{(entry, atom) at I} sum_chi P[entry][chi] C'[atom][2 chi + s][n]
-// (W is not read when beta == 0; the list is empty for nodes outside every support.)
+// (run of kNlRun = 16 consecutive global nodes, 32-column tile):
+//   W[2I+s][n] = beta Wold[2I+s][n] + gamma X[2I+s][n] + rscale[n] Rs[2I+s][n]
+//               + sum_{atoms a at I} sum_chi P[entry(a, I)][chi] C'[a][2 chi + s][n]
+// For each atom meeting the run, the back-product is the complex product of the
+// run's 16 x n_pj projector block with the n_pj x 32 coefficient tile, done as
+// 16x16x4 MFMAs (k = projector index, padded to a multiple of 4; nodes of the run
+// outside the atom's support contribute zero rows).  All operands of an atom are
+// loaded before its MFMAs; each coefficient row is read once per run.  W and
+// Wold are not read when beta == 0, X when gamma == 0, Rs when null.
 template <class T>
 __global__ __launch_bounds__(256) void init_nl_kernel(
-    const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ node_off,
-    const int32_t* __restrict__ nlist_entry, const int32_t* __restrict__ nlist_atom,
+    const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ run_off,
+    const int32_t* __restrict__ pair_atom, const int32_t* __restrict__ pair_ent,
     const int32_t* __restrict__ atom_npj, int max_pj, const typename C2<T>::type* __restrict__ Cp,
     int has_nl, const double2* __restrict__ X, int64_t ldx, double2* W, int64_t ldw,
     const double2* Wold, int64_t ldo, const double2* __restrict__ Rs, int64_t ldr,
-    const double* __restrict__ rscale, int64_t n_nodes, int n_vec, double beta, double gamma) {
+    const double* __restrict__ rscale, int64_t n_nodes, int n_work, int n_coltiles, int n_vec, double beta,
+    double gamma) {
   typedef typename C2<T>::type CT;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t node = __builtin_amdgcn_readfirstlane((int)wid);
-  if (node >= n_nodes) return;
+  typedef typename Vec4<T>::type V4;
+  static_assert(kNlRun == 16, "one MFMA row block per run");
+  constexpr int KS = (kMaxPj + 3) / 4;    // k-steps per atom
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  if (wid >= n_work) return;              // no barrier in this kernel
+  const int run = wid / n_coltiles, ct = wid - run * n_coltiles;
   const int lane = threadIdx.x & 63;
-  const int c0 = blockIdx.y * 128 + lane;
-  double2 w[2][2];          // [column half][spin]
+  const int kl = lane >> 4, il = lane & 15;
+  int col[2];
+  bool cv[2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = c0 + 64 * h;
+  for (int cb = 0; cb < 2; ++cb) {
+    col[cb] = ct * 32 + cb * 16 + il;
+    cv[cb] = col[cb] < n_vec;
+    if (!cv[cb]) col[cb] = n_vec - 1;     // clamped: loads stay in bounds
+  }
+  V4 dr[2][2], di[2][2];                  // [spin][16-column block]
 #pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-      double2 v = {0.0, 0.0};
-      if (col < n_vec) {
-        const int64_t r = 2 * node + sp;
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) dr[sp][cb] = di[sp][cb] = V4{0, 0, 0, 0};
+  if (has_nl) {
+    const int p0 = run_off[run], p1 = run_off[run + 1];
+    for (int pr = p0; pr < p1; ++pr) {
+      const int a = pair_atom[pr];
+      const int npj = atom_npj[a];
+      const int ent = pair_ent[(size_t)pr * kNlRun + il];      // A row = node il of the run
+      const CT* cpa = Cp + (size_t)a * 2 * max_pj * n_vec;
+      CT pa[KS];
+      CT bv[KS][2][2];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int x = 4 * ks + kl;                               // projector index of this lane
+        const bool xv = x < npj;
+        pa[ks] = (xv && ent >= 0) ? proj[(size_t)ent * max_pj + x] : CT{(T)0, (T)0};
+        const int xr = xv ? x : 0;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            const CT v = cpa[(size_t)(2 * xr + sp) * n_vec + col[cb]];
+            bv[ks][sp][cb] = (xv && cv[cb]) ? v : CT{(T)0, (T)0};
+          }
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (4 * ks >= npj) break;                                // wave-uniform
+        const T nai = -pa[ks].y;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            dr[sp][cb] = mfma(pa[ks].x, bv[ks][sp][cb].x, dr[sp][cb]);
+            dr[sp][cb] = mfma(nai, bv[ks][sp][cb].y, dr[sp][cb]);
+            di[sp][cb] = mfma(pa[ks].x, bv[ks][sp][cb].y, di[sp][cb]);
+            di[sp][cb] = mfma(pa[ks].y, bv[ks][sp][cb].x, di[sp][cb]);
+          }
+      }
+    }
+  }
+  // lane holds nodes acc_row(lane, j) of the run, columns col[cb]
+  const int64_t node0 = (int64_t)run * kNlRun;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t node = node0 + acc_row<T>(lane, j);
+    if (node >= n_nodes) continue;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      if (!cv[cb]) continue;
+      const int c = col[cb];
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        const int64_t row = 2 * node + sp;
+        double2 v = {(double)dr[sp][cb][j], (double)di[sp][cb][j]};
         if (beta != 0.0) {
-          const double2 o = Wold[r * ldo + col];
-          v.x = beta * o.x;
-          v.y = beta * o.y;
+          const double2 o = Wold[row * ldo + c];
+          v.x += beta * o.x;
+          v.y += beta * o.y;
         }
         if (gamma != 0.0) {
-          const double2 xv = X[r * ldx + col];
+          const double2 xv = X[row * ldx + c];
           v.x += gamma * xv.x;
           v.y += gamma * xv.y;
         }
         if (Rs) {
-          const double2 rv = Rs[r * ldr + col];
-          const double sc = rscale[col];
+          const double2 rv = Rs[row * ldr + c];
+          const double sc = rscale[c];
           v.x += sc * rv.x;
           v.y += sc * rv.y;
         }
+        W[row * ldw + c] = v;
       }
-      w[h][sp] = v;
-    }
-  }
-  if (has_nl) {
-    const int l0 = node_off[node], l1 = node_off[node + 1];
-    const int mr = 2 * max_pj;
-    T acc[2][2][2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp) acc[h][sp][0] = acc[h][sp][1] = (T)0;
-    for (int t = l0; t < l1; ++t) {
-      const int ent = nlist_entry[t], a = nlist_atom[t];
-      const int npj = atom_npj[a];
-      CT p[kMaxPj];
-#pragma unroll
-      for (int x = 0; x < kMaxPj; ++x) {
-        p[x].x = (T)0;
-        p[x].y = (T)0;
-        if (x < npj) p[x] = proj[(size_t)ent * max_pj + x];
-      }
-      // all coefficient loads of this (entry, atom) are independent
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int col = c0 + 64 * h;
-        if (col >= n_vec) continue;
-#pragma unroll
-        for (int x = 0; x < kMaxPj; ++x) {
-          if (x >= npj) continue;
-#pragma unroll
-          for (int sp = 0; sp < 2; ++sp) {
-            const CT cv = Cp[((size_t)a * mr + 2 * x + sp) * n_vec + col];
-            acc[h][sp][0] += p[x].x * cv.x - p[x].y * cv.y;
-            acc[h][sp][1] += p[x].x * cv.y + p[x].y * cv.x;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp) {
-        w[h][sp].x += (double)acc[h][sp][0];
-        w[h][sp].y += (double)acc[h][sp][1];
-      }
-  }
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int col = c0 + 64 * h;
-    if (col < n_vec) {
-      W[(2 * node) * ldw + col] = w[h][0];
-      W[(2 * node + 1) * ldw + col] = w[h][1];
     }
   }
 }
@@ -355,10 +392,11 @@ static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
   const double nl_bytes = (double)nl.n_entries * (2.0 * n_vec * sizeof(double2) + nl.max_pj * sizeof(CT));
   StageTimer tm(c, CHFSI_STAGE_NONLOCAL, nl_flops, nl_flops, nl_bytes);
   const int nct = cdiv(n_vec, 64);
-  const int n_work = nl.n_chunks * nct;
-  hipLaunchKernelGGL(nl_contract_kernel<T>, dim3(cdiv(n_work, 4)), dim3(256), 0, c->stream, proj,
+  const int nct32 = cdiv(n_vec, 32);
+  const int n_work = nl.n_chunks * nct32;
+  hipLaunchKernelGGL(nl_contract_kernel<T>, dim3(8 * cdiv(cdiv(n_work, 4), 8)), dim3(256), 0, c->stream, proj,
                      nl.sup_node.ptr, nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr,
-                     nl.atom_npj.ptr, nl.max_pj, n_work, nct, X, ldx, n_vec, partial);
+                     nl.chunk_order.ptr, nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X, ldx, n_vec, partial);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(nl_reduce_kernel<T>, dim3(nl.n_atoms, mr, nct), dim3(64), 0, c->stream, partial,
                      nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.max_pj, n_vec, Csum);
@@ -379,11 +417,13 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
   StageTimer tm(c, CHFSI_STAGE_AXPY, Cp ? 8.0 * 2.0 * nl.n_entries * nl.max_pj * n_vec : 0.0, 0.0,
                 (double)rows * n_vec * sizeof(double2) * (1.0 + (beta != 0.0) + (gamma != 0.0)));
   const int has = Cp != nullptr;
-  dim3 grid(cdiv(c->n_nodes, 4), cdiv(n_vec, 128));
-  hipLaunchKernelGGL(init_nl_kernel<T>, grid, dim3(256), 0, c->stream, proj,
-                     has ? nl.node_off.ptr : nullptr, has ? nl.nlist_entry.ptr : nullptr,
-                     has ? nl.nlist_atom.ptr : nullptr, has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has,
-                     X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale, c->n_nodes, n_vec, beta, gamma);
+  const int64_t n_runs = (c->n_nodes + kNlRun - 1) / kNlRun;
+  const int nct = cdiv(n_vec, 32);
+  const int n_work = (int)(n_runs * nct);
+  hipLaunchKernelGGL(init_nl_kernel<T>, dim3(cdiv(n_work, 4)), dim3(256), 0, c->stream, proj,
+                     has ? nl.run_off.ptr : nullptr, has ? nl.pair_atom.ptr : nullptr,
+                     has ? nl.pair_ent.ptr : nullptr, has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has,
+                     X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale, c->n_nodes, n_work, nct, n_vec, beta, gamma);
   LAUNCH_CHECK();
 }
 
