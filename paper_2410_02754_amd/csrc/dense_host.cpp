@@ -10,7 +10,9 @@
 //    accumulating the rotations, and back-transformation.
 // All matrices are row-major std::vector<cplx> of size n*n.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -18,43 +20,86 @@
 
 namespace chfsi {
 
-static int n_threads(size_t work) {
-  int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
-  if (work < (size_t)1 << 16) return 1;
-  return nt;
-}
-
-template <class F>
-static void par_rows(int n, size_t work_per_row, F f) {
-  int nt = n_threads((size_t)n * work_per_row);
-  nt = std::min(nt, std::max(1, n));
-  if (nt <= 1) {
-    for (int i = 0; i < n; ++i) f(i);
-    return;
+// Fixed set of worker threads for the O(n^3) loops below.  run(f) calls f(t, nt)
+// on every worker t (the caller is worker 0) and returns when all are done; the
+// workers spin briefly, then yield, between calls, so the many short parallel
+// phases of one factorisation pay no thread start-up.
+class Pool {
+ public:
+  explicit Pool(size_t work) {
+    nt_ = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if (work < ((size_t)1 << 16)) nt_ = 1;
+    for (int t = 1; t < nt_; ++t) th_.emplace_back([this, t]() { loop(t); });
   }
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&, t]() {
-      for (int i = t; i < n; i += nt) f(i);
-    });
-  for (auto& x : th) x.join();
-}
+  ~Pool() {
+    stop_.store(true);
+    gen_.fetch_add(1);
+    for (auto& x : th_) x.join();
+  }
+  int size() const { return nt_; }
+  void run(const std::function<void(int, int)>& f) {
+    if (nt_ == 1) {
+      f(0, 1);
+      return;
+    }
+    f_ = &f;
+    done_.store(0);
+    gen_.fetch_add(1, std::memory_order_release);
+    f(0, nt_);
+    for (int spin = 0; done_.load(std::memory_order_acquire) != nt_ - 1; ++spin)
+      if (spin > 4096) std::this_thread::yield();
+  }
+  // [lo, hi) share of n items for worker t of nt
+  static void range(int n, int t, int nt, int& lo, int& hi) {
+    lo = (int)((int64_t)n * t / nt);
+    hi = (int)((int64_t)n * (t + 1) / nt);
+  }
+
+ private:
+  void loop(int t) {
+    unsigned seen = 0;
+    while (true) {
+      unsigned g;
+      for (int spin = 0; (g = gen_.load(std::memory_order_acquire)) == seen; ++spin)
+        if (spin > 4096) std::this_thread::yield();
+      seen = g;
+      if (stop_.load()) return;
+      (*f_)(t, nt_);
+      done_.fetch_add(1, std::memory_order_acq_rel);
+    }
+  }
+  int nt_ = 1;
+  std::vector<std::thread> th_;
+  std::atomic<unsigned> gen_{0};
+  std::atomic<int> done_{0};
+  std::atomic<bool> stop_{false};
+  const std::function<void(int, int)>* f_ = nullptr;
+};
 
 int cholesky_lower(std::vector<cplx>& S, int n) {
-  // in place: lower triangle of S becomes L, upper triangle zeroed
+  // in place, left-looking by rows of columns: lower triangle of S becomes L,
+  // upper triangle zeroed; the updates of the rows below column j run in parallel
+  Pool pool((size_t)n * n * n / 3);
   for (int j = 0; j < n; ++j) {
     double d = S[(size_t)j * n + j].real();
     for (int k = 0; k < j; ++k) d -= std::norm(S[(size_t)j * n + k]);
     if (!(d > 0.0) || !std::isfinite(d)) return j;
     const double ljj = std::sqrt(d);
     S[(size_t)j * n + j] = ljj;
-    for (int i = j + 1; i < n; ++i) {
-      cplx s = S[(size_t)i * n + j];
-      const cplx* Li = &S[(size_t)i * n];
+    const int rows = n - j - 1;
+    auto body = [&](int t, int nt) {
+      int lo, hi;
+      Pool::range(rows, t, nt, lo, hi);
       const cplx* Lj = &S[(size_t)j * n];
-      for (int k = 0; k < j; ++k) s -= Li[k] * std::conj(Lj[k]);
-      S[(size_t)i * n + j] = s / ljj;
-    }
+      for (int i = j + 1 + lo; i < j + 1 + hi; ++i) {
+        cplx s = S[(size_t)i * n + j];
+        const cplx* Li = &S[(size_t)i * n];
+        for (int k = 0; k < j; ++k) s -= Li[k] * std::conj(Lj[k]);
+        S[(size_t)i * n + j] = s / ljj;
+      }
+    };
+    if ((size_t)rows * j > 4096) pool.run(body);
+    else body(0, 1);
   }
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) S[(size_t)i * n + j] = 0.0;
@@ -63,29 +108,38 @@ int cholesky_lower(std::vector<cplx>& S, int n) {
 
 void lower_inverse(const std::vector<cplx>& L, int n, std::vector<cplx>& X) {
   X.assign((size_t)n * n, cplx(0.0, 0.0));
-  // column j of X solves L x = e_j; columns are independent
-  std::vector<std::vector<cplx>> cols(n);
-  par_rows(n, (size_t)n * n / 2, [&](int j) {
-    std::vector<cplx> x(n, 0.0);
-    x[j] = 1.0 / L[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      cplx s = 0.0;
-      const cplx* Li = &L[(size_t)i * n];
-      for (int k = j; k < i; ++k) s += Li[k] * x[k];
-      x[i] = -s / L[(size_t)i * n + i];
+  // column j of X solves L x = e_j; columns are independent (interleaved over
+  // the workers, since column j costs ~(n - j)^2)
+  Pool pool((size_t)n * n * n / 6);
+  pool.run([&](int t, int nt) {
+    std::vector<cplx> x(n);
+    for (int j = t; j < n; j += nt) {
+      x[j] = 1.0 / L[(size_t)j * n + j];
+      for (int i = j + 1; i < n; ++i) {
+        cplx s = 0.0;
+        const cplx* Li = &L[(size_t)i * n];
+        for (int k = j; k < i; ++k) s += Li[k] * x[k];
+        x[i] = -s / L[(size_t)i * n + i];
+      }
+      for (int i = j; i < n; ++i) X[(size_t)i * n + j] = x[i];
     }
-    cols[j].swap(x);
   });
-  for (int j = 0; j < n; ++j)
-    for (int i = j; i < n; ++i) X[(size_t)i * n + j] = cols[j][i];
 }
 
 // Implicit QL on the real symmetric tridiagonal (d, e), e[i] couples i, i+1.
-// Zt[i][:] accumulates eigenvector i (rows), starting from the identity.
-static void tridiag_ql(std::vector<double>& d, std::vector<double>& e, std::vector<double>* Zt, int n) {
+// Zt[i][:] accumulates eigenvector i (rows), starting from the identity.  The
+// rotations only act on Zt, so they are recorded in order and applied after the
+// iteration, each worker applying all of them to its own range of columns.  One
+// QL step is a chain of rotations of rows (i, i+1), i = m-1 down to l; along the
+// chain the updated row i is the next rotation's row i+1, so it stays in
+// registers ("carry") and each rotation costs one row load and one row store.
+static void tridiag_ql(std::vector<double>& d, std::vector<double>& e, std::vector<double>* Zt, int n,
+                       Pool* pool) {
   if (n == 0) return;
   e.resize(n);
   e[n - 1] = 0.0;
+  std::vector<int> ch_m, ch_len;           // chain: rotations of rows (i, i+1), i = m-1 .. m-len
+  std::vector<double> rc, rs;
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     while (true) {
@@ -102,6 +156,7 @@ static void tridiag_ql(std::vector<double>& d, std::vector<double>& e, std::vect
       double s = 1.0, c = 1.0, p = 0.0;
       int i = m - 1;
       bool deflated = false;
+      const size_t first = rc.size();
       for (; i >= l; --i) {
         double f = s * e[i], b = c * e[i];
         r = std::hypot(f, g);
@@ -120,14 +175,13 @@ static void tridiag_ql(std::vector<double>& d, std::vector<double>& e, std::vect
         d[i + 1] = g + p;
         g = c * r - b;
         if (Zt) {
-          double* zi = &(*Zt)[(size_t)i * n];
-          double* zj = &(*Zt)[(size_t)(i + 1) * n];
-          for (int k = 0; k < n; ++k) {
-            const double t = zj[k];
-            zj[k] = s * zi[k] + c * t;
-            zi[k] = c * zi[k] - s * t;
-          }
+          rc.push_back(c);
+          rs.push_back(s);
         }
+      }
+      if (Zt && rc.size() > first) {
+        ch_m.push_back(m);
+        ch_len.push_back((int)(rc.size() - first));
       }
       if (deflated) continue;
       d[l] -= p;
@@ -135,9 +189,50 @@ static void tridiag_ql(std::vector<double>& d, std::vector<double>& e, std::vect
       e[m] = 0.0;
     }
   }
+  if (!Zt || rc.empty()) return;
+  auto body = [&](int t, int nt) {
+    int lo, hi;
+    Pool::range(n, t, nt, lo, hi);
+    double* Z = Zt->data();
+    constexpr int B = 8;
+    for (int k0 = lo; k0 < hi; k0 += B) {
+      const int w = std::min(B, hi - k0);
+      size_t q = 0;
+      for (size_t ch = 0; ch < ch_m.size(); ++ch) {
+        const int m = ch_m[ch], len = ch_len[ch];
+        double carry[B];
+        const double* zm = Z + (size_t)m * n + k0;
+        for (int u = 0; u < B; ++u) carry[u] = u < w ? zm[u] : 0.0;
+        for (int r = 0; r < len; ++r, ++q) {
+          const int i = m - 1 - r;
+          double* __restrict__ zi = Z + (size_t)i * n + k0;
+          double* __restrict__ zj = zi + n;
+          const double c = rc[q], s = rs[q];
+          if (w == B) {
+            for (int u = 0; u < B; ++u) {
+              const double a = zi[u];
+              zj[u] = s * a + c * carry[u];
+              carry[u] = c * a - s * carry[u];
+            }
+          } else {
+            for (int u = 0; u < w; ++u) {
+              const double a = zi[u];
+              zj[u] = s * a + c * carry[u];
+              carry[u] = c * a - s * carry[u];
+            }
+          }
+        }
+        double* zl = Z + (size_t)(m - len) * n + k0;
+        for (int u = 0; u < w; ++u) zl[u] = carry[u];
+      }
+    }
+  };
+  if (pool) pool->run(body);
+  else body(0, 1);
 }
 
 void hermitian_eig(const std::vector<cplx>& Ain, int n, std::vector<double>& w, std::vector<cplx>& V) {
+  Pool pool((size_t)n * n * n);
   std::vector<cplx> A = Ain;
   // use the lower triangle; make A exactly Hermitian from it
   for (int i = 0; i < n; ++i) {
@@ -168,20 +263,46 @@ void hermitian_eig(const std::vector<cplx>& Ain, int n, std::vector<double>& w, 
     vn = std::sqrt(vn);
     for (int i = 0; i < m; ++i) v[i] /= vn;
     // p = A_sub v ; rho = v^H p ; q = p - rho v ; A_sub -= 2 (v q^H + q v^H)
-    par_rows(m, (size_t)m, [&](int i) {
-      cplx s = 0.0;
-      const cplx* Ai = &A[(size_t)(k + 1 + i) * n + k + 1];
-      for (int j = 0; j < m; ++j) s += Ai[j] * v[j];
-      p[i] = s;
-    });
+    const bool par = (size_t)m * m > 8192;
+    auto matvec = [&](int t, int nt) {
+      int lo, hi;
+      Pool::range(m, t, nt, lo, hi);
+      const double* vv = reinterpret_cast<const double*>(v.data());
+      for (int i = lo; i < hi; ++i) {
+        const double* Ai = reinterpret_cast<const double*>(&A[(size_t)(k + 1 + i) * n + k + 1]);
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < m; ++j) {
+          sr += Ai[2 * j] * vv[2 * j] - Ai[2 * j + 1] * vv[2 * j + 1];
+          si += Ai[2 * j] * vv[2 * j + 1] + Ai[2 * j + 1] * vv[2 * j];
+        }
+        p[i] = cplx(sr, si);
+      }
+    };
+    if (par) pool.run(matvec);
+    else matvec(0, 1);
     cplx rho = 0.0;
     for (int i = 0; i < m; ++i) rho += std::conj(v[i]) * p[i];
     for (int i = 0; i < m; ++i) q[i] = p[i] - rho.real() * v[i];
-    par_rows(m, (size_t)m, [&](int i) {
-      cplx* Ai = &A[(size_t)(k + 1 + i) * n + k + 1];
-      const cplx vi = v[i], qi = q[i];
-      for (int j = 0; j < m; ++j) Ai[j] -= 2.0 * (vi * std::conj(q[j]) + qi * std::conj(v[j]));
-    });
+    auto update = [&](int t, int nt) {
+      int lo, hi;
+      Pool::range(m, t, nt, lo, hi);
+      const double* vv = reinterpret_cast<const double*>(v.data());
+      const double* qq = reinterpret_cast<const double*>(q.data());
+      for (int i = lo; i < hi; ++i) {
+        double* Ai = reinterpret_cast<double*>(&A[(size_t)(k + 1 + i) * n + k + 1]);
+        const double vr = 2.0 * v[i].real(), vim = 2.0 * v[i].imag();
+        const double qr = 2.0 * q[i].real(), qim = 2.0 * q[i].imag();
+        for (int j = 0; j < m; ++j) {
+          // vi conj(q_j) + qi conj(v_j)
+          const double ar = vr * qq[2 * j] + vim * qq[2 * j + 1] + qr * vv[2 * j] + qim * vv[2 * j + 1];
+          const double ai = vim * qq[2 * j] - vr * qq[2 * j + 1] + qim * vv[2 * j] - qr * vv[2 * j + 1];
+          Ai[2 * j] -= ar;
+          Ai[2 * j + 1] -= ai;
+        }
+      }
+    };
+    if (par) pool.run(update);
+    else update(0, 1);
     offd[k] = alpha;
     for (int i = 1; i < m; ++i) {
       A[(size_t)(k + 1 + i) * n + k] = 0.0;
@@ -203,7 +324,7 @@ void hermitian_eig(const std::vector<cplx>& Ain, int n, std::vector<double>& w, 
   }
   std::vector<double> Zt((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
-  tridiag_ql(d, e, &Zt, n);
+  tridiag_ql(d, e, &Zt, n, &pool);
   // sort ascending
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -216,28 +337,42 @@ void hermitian_eig(const std::vector<cplx>& Ain, int n, std::vector<double>& w, 
     const double* z = &Zt[(size_t)order[j] * n];
     for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = phi[i] * z[i];
   }
-  // Q = H_0 H_1 ... H_{n-3}; apply in reverse to the rows k+1.. of V
-  for (int k = n - 3; k >= 0; --k) {
-    const auto& v = vs[k];
-    if (v.empty()) continue;
-    const int m = n - k - 1;
-    std::vector<cplx> t(n, 0.0);     // t = v^H V_sub
-    for (int i = 0; i < m; ++i) {
-      const cplx cv = std::conj(v[i]);
-      const cplx* Vi = &V[(size_t)(k + 1 + i) * n];
-      for (int j = 0; j < n; ++j) t[j] += cv * Vi[j];
+  // Q = H_0 H_1 ... H_{n-3}; apply in reverse to the rows k+1.. of V, each
+  // worker on its own range of columns (the columns are independent)
+  pool.run([&](int t, int nt) {
+    int lo, hi;
+    Pool::range(n, t, nt, lo, hi);
+    if (lo >= hi) return;
+    const int w2 = 2 * (hi - lo);
+    std::vector<double> tv(w2);
+    for (int k = n - 3; k >= 0; --k) {
+      const auto& v = vs[k];
+      if (v.empty()) continue;
+      const int m = n - k - 1;
+      std::fill(tv.begin(), tv.end(), 0.0);               // t = v^H V_sub
+      for (int i = 0; i < m; ++i) {
+        const double cr = v[i].real(), ci = -v[i].imag();
+        const double* Vi = reinterpret_cast<const double*>(&V[(size_t)(k + 1 + i) * n + lo]);
+        for (int j = 0; j < w2; j += 2) {
+          tv[j] += cr * Vi[j] - ci * Vi[j + 1];
+          tv[j + 1] += cr * Vi[j + 1] + ci * Vi[j];
+        }
+      }
+      for (int i = 0; i < m; ++i) {
+        const double vr = 2.0 * v[i].real(), vim = 2.0 * v[i].imag();
+        double* Vi = reinterpret_cast<double*>(&V[(size_t)(k + 1 + i) * n + lo]);
+        for (int j = 0; j < w2; j += 2) {
+          Vi[j] -= vr * tv[j] - vim * tv[j + 1];
+          Vi[j + 1] -= vr * tv[j + 1] + vim * tv[j];
+        }
+      }
     }
-    par_rows(m, (size_t)n, [&](int i) {
-      cplx* Vi = &V[(size_t)(k + 1 + i) * n];
-      const cplx vi = 2.0 * v[i];
-      for (int j = 0; j < n; ++j) Vi[j] -= vi * t[j];
-    });
-  }
+  });
 }
 
 void tridiag_eigvals(std::vector<double> d, std::vector<double> e, std::vector<double>& w) {
   const int n = (int)d.size();
-  tridiag_ql(d, e, nullptr, n);
+  tridiag_ql(d, e, nullptr, n, nullptr);
   std::sort(d.begin(), d.end());
   w = d;
 }

@@ -263,8 +263,11 @@ __global__ __launch_bounds__(64) void nl_delta_kernel(const typename C2<T>::type
 // 16x16x4 MFMAs (k = projector index, padded to a multiple of 4; nodes of the run
 // outside the atom's support contribute zero rows).  All operands of an atom are
 // loaded before its MFMAs; each coefficient row is read once per run.  W and
-// Wold are not read when beta == 0, X when gamma == 0, Rs when null.
-template <class T>
+// Wold are not read without the beta term, X without the gamma term, Rs without
+// the residual term (FL: which terms are present).
+constexpr int kInitBeta = 1, kInitGamma = 2, kInitRs = 4;
+
+template <class T, int FL>
 __global__ __launch_bounds__(256) void init_nl_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ run_off,
     const int32_t* __restrict__ pair_atom, const int32_t* __restrict__ pair_ent,
@@ -334,39 +337,46 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
       }
     }
   }
-  // lane holds nodes acc_row(lane, j) of the run, columns col[cb]
+  // lane holds nodes acc_row(lane, j) of the run, columns col[cb]; every load of
+  // the epilogue is issued unconditionally (clamped rows) and only the stores
+  // are predicated
   const int64_t node0 = (int64_t)run * kNlRun;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t node = node0 + acc_row<T>(lane, j);
-    if (node >= n_nodes) continue;
+    const bool nv = node < n_nodes;
+    const int64_t nodec = nv ? node : n_nodes - 1;
+    double2 v[2][2];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      if (!cv[cb]) continue;
-      const int c = col[cb];
+    for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) {
-        const int64_t row = 2 * node + sp;
-        double2 v = {(double)dr[sp][cb][j], (double)di[sp][cb][j]};
-        if (beta != 0.0) {
+        const int64_t row = 2 * nodec + sp;
+        const int c = col[cb];
+        double2 t = {(double)dr[sp][cb][j], (double)di[sp][cb][j]};
+        if (FL & kInitBeta) {
           const double2 o = Wold[row * ldo + c];
-          v.x += beta * o.x;
-          v.y += beta * o.y;
+          t.x += beta * o.x;
+          t.y += beta * o.y;
         }
-        if (gamma != 0.0) {
+        if (FL & kInitGamma) {
           const double2 xv = X[row * ldx + c];
-          v.x += gamma * xv.x;
-          v.y += gamma * xv.y;
+          t.x += gamma * xv.x;
+          t.y += gamma * xv.y;
         }
-        if (Rs) {
+        if (FL & kInitRs) {
           const double2 rv = Rs[row * ldr + c];
           const double sc = rscale[c];
-          v.x += sc * rv.x;
-          v.y += sc * rv.y;
+          t.x += sc * rv.x;
+          t.y += sc * rv.y;
         }
-        W[row * ldw + c] = v;
+        v[cb][sp] = t;
       }
-    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp)
+        if (nv && cv[cb]) W[(2 * node + sp) * ldw + col[cb]] = v[cb][sp];
   }
 }
 
@@ -420,10 +430,23 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
   const int64_t n_runs = (c->n_nodes + kNlRun - 1) / kNlRun;
   const int nct = cdiv(n_vec, 32);
   const int n_work = (int)(n_runs * nct);
-  hipLaunchKernelGGL(init_nl_kernel<T>, dim3(cdiv(n_work, 4)), dim3(256), 0, c->stream, proj,
-                     has ? nl.run_off.ptr : nullptr, has ? nl.pair_atom.ptr : nullptr,
-                     has ? nl.pair_ent.ptr : nullptr, has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has,
-                     X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale, c->n_nodes, n_work, nct, n_vec, beta, gamma);
+  const int fl = (beta != 0.0 ? kInitBeta : 0) | (gamma != 0.0 ? kInitGamma : 0) | (Rs ? kInitRs : 0);
+  const dim3 grid(cdiv(n_work, 4)), blk(256);
+#define INIT_NL_ARGS                                                                                      \
+  proj, has ? nl.run_off.ptr : nullptr, has ? nl.pair_atom.ptr : nullptr, has ? nl.pair_ent.ptr : nullptr, \
+      has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has, X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale,    \
+      c->n_nodes, n_work, nct, n_vec, beta, gamma
+  switch (fl) {
+    case 0: hipLaunchKernelGGL((init_nl_kernel<T, 0>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    case 1: hipLaunchKernelGGL((init_nl_kernel<T, 1>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    case 2: hipLaunchKernelGGL((init_nl_kernel<T, 2>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    case 3: hipLaunchKernelGGL((init_nl_kernel<T, 3>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    case 4: hipLaunchKernelGGL((init_nl_kernel<T, 4>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    case 5: hipLaunchKernelGGL((init_nl_kernel<T, 5>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    case 6: hipLaunchKernelGGL((init_nl_kernel<T, 6>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    default: hipLaunchKernelGGL((init_nl_kernel<T, 7>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+  }
+#undef INIT_NL_ARGS
   LAUNCH_CHECK();
 }
 
@@ -754,11 +777,21 @@ void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t
 // 32 rows x 32 columns complex, block 64 x 64.  upper: Q[k][j] = 0 for k > j.
 __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__ P, int n,
                                                      int64_t prow, const double2* __restrict__ Q,
-                                                     double2* __restrict__ X, int64_t ldx, int upper) {
+                                                     double2* __restrict__ X, int64_t ldx, int upper,
+                                                     int n_rb, int n_cb) {
+  // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each XCD
+  // takes a contiguous range of (row block, column block) tiles, column block
+  // fastest: the column blocks of one row block run together and read the
+  // panel rows through the same L2.
+  const int n_work = n_rb * n_cb;
+  const int per_xcd = (int)((gridDim.x + 7) / 8);
+  const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (bid >= n_work) return;              // uniform over the block; no barrier here
+  const int rb = bid / n_cb, cbk = bid - rb * n_cb;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t rbase = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
-  const int j0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int kend = upper ? std::min(n, (int)(blockIdx.y * 64 + 64)) : n;
+  const int64_t rbase = (int64_t)rb * 64 + (wave & 1) * 32;
+  const int j0 = cbk * 64 + (wave >> 1) * 32;
+  const int kend = upper ? std::min(n, cbk * 64 + 64) : n;
   d4 cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -816,9 +849,10 @@ void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n, 
   for (int64_t r0 = 0; r0 < rows; r0 += prow) {
     const int64_t pr = std::min(prow, rows - r0);
     launch_copy_rows(c, P, n, X + r0 * ldx, ldx, pr, n);
-    dim3 grid(cdiv(pr, 64), cdiv(n, 64));
-    hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, c->stream, P, n, pr, Qd, X + r0 * ldx, ldx,
-                       upper ? 1 : 0);
+    const int n_rb = cdiv(pr, 64), n_cb = cdiv(n, 64);
+    const int grid = 8 * cdiv((int64_t)n_rb * n_cb, 8);
+    hipLaunchKernelGGL(rotate_kernel, dim3(grid), dim3(256), 0, c->stream, P, n, pr, Qd, X + r0 * ldx, ldx,
+                       upper ? 1 : 0, n_rb, n_cb);
     LAUNCH_CHECK();
   }
   CHFSI_HIP(hipStreamSynchronize(c->stream));   // qh leaves scope
