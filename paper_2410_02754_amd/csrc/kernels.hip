@@ -665,69 +665,138 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
 // ============================================================================
 // Dense tall-skinny products (FP64 MFMA) for CholGS and Rayleigh-Ritz
 // ============================================================================
-// Partial S = X^H Y over a chunk of rows.  Wave tile 32 x 32 complex
-// (2 x 2 MFMA blocks), block = 4 waves = 64 x 64 tile.  Fragments come straight
-// from global memory: A[i][k] = X[row k][col i], B[k][j] = Y[row k][col j].
-__global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X, int64_t ldx,
-                                                   const double2* __restrict__ Y, int64_t ldy,
-                                                   int64_t rows, int n, int64_t chunk_rows,
-                                                   const int2* __restrict__ tiles,
-                                                   double2* __restrict__ partial) {
-  const int2 tl = tiles[blockIdx.x];
-  const int chunk = blockIdx.y;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i0 = tl.x * 64 + (wave & 1) * 32, j0 = tl.y * 64 + (wave >> 1) * 32;
-  const int64_t r_begin = chunk * chunk_rows;
-  const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
-  d4 sr[2][2], si[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) sr[a][b] = si[a][b] = d4{0, 0, 0, 0};
+// Both products run on one LDS-staged tile engine: workgroup tile 128 x 64
+// complex outputs, 4 waves of 64 x 32 (4 x 2 blocks of 16 x 16, 4 real MFMAs
+// per complex block and k-step of 4), k staged through LDS in double-buffered
+// stages of 8, k-major ([k][m] and [k][n]) so that every fragment read is 16
+// consecutive complex values.  The next stage's global loads are issued before
+// the current stage's MFMAs.
+constexpr int kGM = 128, kGN = 64, kGK = 8, kGPad = 4;
+
+struct GemmSmem {
+  double2 a[2][kGK][kGM + kGPad];
+  double2 b[2][kGK][kGN + kGPad];
+};
+
+// acc[mb][nb] (re, im) += op(A) B over one LDS stage; CONJ: op(A) = conj(A)
+template <bool CONJ>
+__device__ __forceinline__ void gemm_stage(const GemmSmem& sm, int buf, int wm, int wn, int lane, d4 (&cr)[4][2],
+                                           d4 (&ci)[4][2]) {
   const int kl = lane >> 4, il = lane & 15;
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += 4) {
-    const int64_t r = r0 + kl;
-    double2 xa[2], yb[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int ci = i0 + a * 16 + il, cj = j0 + a * 16 + il;
-      xa[a] = (r < r_end && ci < n) ? X[r * ldx + ci] : double2{0.0, 0.0};
-      yb[a] = (r < r_end && cj < n) ? Y[r * ldy + cj] : double2{0.0, 0.0};
-    }
+  for (int ks = 0; ks < kGK / 4; ++ks) {
+    double2 fa[4], fb[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const double nxi = -xa[a].y;
+    for (int mb = 0; mb < 4; ++mb) fa[mb] = sm.a[buf][ks * 4 + kl][wm * 64 + mb * 16 + il];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        sr[a][b] = mfma(xa[a].x, yb[b].x, sr[a][b]);
-        sr[a][b] = mfma(xa[a].y, yb[b].y, sr[a][b]);
-        si[a][b] = mfma(xa[a].x, yb[b].y, si[a][b]);
-        si[a][b] = mfma(nxi, yb[b].x, si[a][b]);
+    for (int nb = 0; nb < 2; ++nb) fb[nb] = sm.b[buf][ks * 4 + kl][wn * 32 + nb * 16 + il];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const double ar = fa[mb].x, ai = CONJ ? -fa[mb].y : fa[mb].y, nai = -ai;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        cr[mb][nb] = mfma(ar, fb[nb].x, cr[mb][nb]);
+        cr[mb][nb] = mfma(nai, fb[nb].y, cr[mb][nb]);
+        ci[mb][nb] = mfma(ar, fb[nb].y, ci[mb][nb]);
+        ci[mb][nb] = mfma(ai, fb[nb].x, ci[mb][nb]);
       }
     }
   }
-  double2* out = partial + (size_t)chunk * n * n;
+}
+
+// Partial S = X^H Y over chunks of rows, lower-triangle tiles only when asked.
+// Work item = (tile, chunk group g); group g walks the row chunks g, g + G, ...
+// and the items of one group are consecutive on one XCD, so the tiles reading
+// the same rows share that XCD's L2.  partial[g] holds the group's n x n sum.
+__global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X, int64_t ldx,
+                                                   const double2* __restrict__ Y, int64_t ldy,
+                                                   int64_t rows, int n, int64_t chunk_rows, int n_groups,
+                                                   const int2* __restrict__ tiles, int n_tiles,
+                                                   double2* __restrict__ partial) {
+  __shared__ GemmSmem sm;
+  const int n_work = n_tiles * n_groups;
+  const int per_xcd = (int)((gridDim.x + 7) / 8);
+  const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+  if (bid >= n_work) return;              // uniform over the block, before any barrier
+  const int g = bid / n_tiles;
+  const int2 tl = tiles[bid - g * n_tiles];
+  const int i0 = tl.x * kGM, j0 = tl.y * kGN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave & 1, wn = wave >> 1;
+  // staging map: A 8 rows x 128 cols (4 per thread), B 8 rows x 64 cols (2 per thread)
+  const int ak = tid >> 5, am = (tid & 31) * 4;
+  const int bk = tid >> 5, bn = (tid & 31) * 2;
+  d4 cr[4][2], ci[4][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int nb = 0; nb < 2; ++nb) cr[mb][nb] = ci[mb][nb] = d4{0, 0, 0, 0};
+  const int64_t n_chunks = (rows + chunk_rows - 1) / chunk_rows;
+  double2 pa[4], pb[2];
+  auto gload = [&](int64_t r0, int64_t r_end) {
+    const int64_t r = r0 + ak;
+    const bool rv = r < r_end;
+    const double2* xp = X + (rv ? r : 0) * ldx;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = i0 + am + u;
+      pa[u] = (rv && c < n) ? xp[c] : double2{0.0, 0.0};
+    }
+    const int64_t rb = r0 + bk;
+    const bool rbv = rb < r_end;
+    const double2* yp = Y + (rbv ? rb : 0) * ldy;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c = j0 + bn + u;
+      pb[u] = (rbv && c < n) ? yp[c] : double2{0.0, 0.0};
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sm.a[buf][ak][am + u] = pa[u];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + u] = pb[u];
+  };
+  for (int64_t ch = g; ch < n_chunks; ch += n_groups) {
+    const int64_t r_begin = ch * chunk_rows;
+    const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
+    const int nst = (int)((r_end - r_begin + kGK - 1) / kGK);
+    __syncthreads();                      // previous chunk's last stage is read
+    gload(r_begin, r_end);
+    lstore(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nst;
+      if (more) gload(r_begin + (int64_t)(st + 1) * kGK, r_end);
+      gemm_stage<true>(sm, buf, wm, wn, lane, cr, ci);
+      if (more) lstore(buf ^ 1);          // that buffer was last read before the previous barrier
+      __syncthreads();
+    }
+  }
+  double2* out = partial + (size_t)g * n * n;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int ri = i0 + a * 16 + acc_row<double>(lane, j);
-        const int cj = j0 + b * 16 + (lane & 15);
-        if (ri < n && cj < n) out[(size_t)ri * n + cj] = double2{sr[a][b][j], si[a][b][j]};
+        const int ri = i0 + wm * 64 + mb * 16 + acc_row<double>(lane, j);
+        const int cj = j0 + wn * 32 + nb * 16 + (lane & 15);
+        if (ri < n && cj < n) out[(size_t)ri * n + cj] = double2{cr[mb][nb][j], ci[mb][nb][j]};
       }
 }
 
-__global__ void gram_reduce_kernel(const double2* __restrict__ partial, int n_chunks, int n,
+// S[i][j] = sum over groups of partial[g][i][j] for the (i, j) of the listed tiles
+__global__ void gram_reduce_kernel(const double2* __restrict__ partial, int n_groups, int n,
                                    const int2* __restrict__ tiles, double2* __restrict__ S) {
   const int2 tl = tiles[blockIdx.x];
-  for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) {
-    const int i = tl.x * 64 + t / 64, j = tl.y * 64 + t % 64;
+  for (int t = threadIdx.x; t < kGM * kGN; t += blockDim.x) {
+    const int i = tl.x * kGM + t / kGN, j = tl.y * kGN + t % kGN;
     if (i >= n || j >= n) continue;
     double2 s = {0.0, 0.0};
-    for (int c = 0; c < n_chunks; ++c) {
-      const double2 v = partial[((size_t)c * n + i) * n + j];
+    for (int g = 0; g < n_groups; ++g) {
+      const double2 v = partial[((size_t)g * n + i) * n + j];
       s.x += v.x;
       s.y += v.y;
     }
@@ -737,28 +806,30 @@ __global__ void gram_reduce_kernel(const double2* __restrict__ partial, int n_ch
 
 void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t ldy, int64_t rows,
           int n, std::vector<cplx>& S, bool lower_only) {
-  const int nt = cdiv(n, 64);
+  const int nti = cdiv(n, kGM), ntj = cdiv(n, kGN);
   std::vector<int2> tiles;
-  for (int i = 0; i < nt; ++i)
-    for (int j = 0; j < nt; ++j)
-      if (!lower_only || j <= i) tiles.push_back(int2{i, j});
+  for (int i = 0; i < nti; ++i)
+    for (int j = 0; j < ntj; ++j)
+      if (!lower_only || j * kGN < (i + 1) * kGM) tiles.push_back(int2{i, j});
   const int ntl = (int)tiles.size();
-  int n_chunks = std::max(1, std::min<int>(2048 / ntl, cdiv(rows, 256)));
-  int64_t chunk_rows = (rows + n_chunks - 1) / n_chunks;
-  chunk_rows = (chunk_rows + 3) / 4 * 4;
-  n_chunks = cdiv(rows, chunk_rows);
-  const size_t need = (size_t)n_chunks * n * n + (size_t)n * n;   // double2 units
+  // one resident round of work items (two 256-thread workgroups per CU at this
+  // kernel's register use); row chunks of 256
+  const int64_t chunk_rows = 256;
+  const int64_t n_chunks = std::max<int64_t>(1, (rows + chunk_rows - 1) / chunk_rows);
+  const int n_groups = (int)std::max<int64_t>(1, std::min<int64_t>(n_chunks, 512 / ntl));
+  const size_t need = (size_t)n_groups * n * n + (size_t)n * n;   // double2 units
   c->scratch.alloc(2 * need + ntl);                               // + tiles (int2 = 1 double)
   double2* partial = reinterpret_cast<double2*>(c->scratch.ptr);
-  double2* Sd = partial + (size_t)n_chunks * n * n;
+  double2* Sd = partial + (size_t)n_groups * n * n;
   int2* td = reinterpret_cast<int2*>(Sd + (size_t)n * n);
   CHFSI_HIP(hipMemcpyAsync(td, tiles.data(), ntl * sizeof(int2), hipMemcpyHostToDevice, c->stream));
-  StageTimer tm(c, CHFSI_STAGE_GRAM, 8.0 * (double)rows * n * n * ((double)ntl / (nt * nt)),
-                8.0 * (double)rows * 4096.0 * ntl, 2.0 * (double)rows * n * sizeof(double2));
-  hipLaunchKernelGGL(gram_kernel, dim3(ntl, n_chunks), dim3(256), 0, c->stream, X, ldx, Y, ldy, rows, n,
-                     chunk_rows, td, partial);
+  StageTimer tm(c, CHFSI_STAGE_GRAM, 8.0 * (double)rows * n * n * (lower_only ? 0.5 : 1.0),
+                8.0 * (double)rows * kGM * kGN * ntl, 2.0 * (double)rows * n * sizeof(double2));
+  const int n_work = ntl * n_groups;
+  hipLaunchKernelGGL(gram_kernel, dim3(8 * cdiv(n_work, 8)), dim3(256), 0, c->stream, X, ldx, Y, ldy, rows, n,
+                     chunk_rows, n_groups, td, ntl, partial);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(ntl), dim3(256), 0, c->stream, partial, n_chunks, n, td, Sd);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(ntl), dim3(256), 0, c->stream, partial, n_groups, n, td, Sd);
   LAUNCH_CHECK();
   std::vector<double2> h((size_t)n * n);
   CHFSI_HIP(hipMemcpyAsync(h.data(), Sd, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
@@ -773,71 +844,87 @@ void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t
     }
 }
 
-// X[r0 + r][:] = P[r][:] Q over a row panel P (a copy of those rows).  Wave tile
-// 32 rows x 32 columns complex, block 64 x 64.  upper: Q[k][j] = 0 for k > j.
+// X[r0 + r][:] = P[r][:] Q over a row panel P (a copy of those rows).  upper:
+// Q[k][j] = 0 for k > j, so the k range of a column tile ends at its last column.
+// Work item = (row tile, column tile), column tile fastest and consecutive on one
+// XCD, so the column tiles of one row tile read its panel rows through one L2.
 __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__ P, int n,
                                                      int64_t prow, const double2* __restrict__ Q,
                                                      double2* __restrict__ X, int64_t ldx, int upper,
-                                                     int n_rb, int n_cb) {
-  // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each XCD
-  // takes a contiguous range of (row block, column block) tiles, column block
-  // fastest: the column blocks of one row block run together and read the
-  // panel rows through the same L2.
-  const int n_work = n_rb * n_cb;
+                                                     int n_rt, int n_ct) {
+  __shared__ GemmSmem sm;
+  const int n_work = n_rt * n_ct;
   const int per_xcd = (int)((gridDim.x + 7) / 8);
   const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-  if (bid >= n_work) return;              // uniform over the block; no barrier here
-  const int rb = bid / n_cb, cbk = bid - rb * n_cb;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t rbase = (int64_t)rb * 64 + (wave & 1) * 32;
-  const int j0 = cbk * 64 + (wave >> 1) * 32;
-  const int kend = upper ? std::min(n, cbk * 64 + 64) : n;
-  d4 cr[2][2], ci[2][2];
+  if (bid >= n_work) return;              // uniform over the block, before any barrier
+  const int rt = bid / n_ct, ct = bid - rt * n_ct;
+  const int64_t r0 = (int64_t)rt * kGM;
+  const int j0 = ct * kGN;
+  const int kend = upper ? std::min(n, j0 + kGN) : n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave & 1, wn = wave >> 1;
+  // staging map: A 128 panel rows x 8 k (4 consecutive k per thread, stored
+  // k-major), B 8 rows of Q x 64 columns (2 per thread)
+  const int am = tid >> 1, ak = (tid & 1) * 4;
+  const int bk = tid >> 5, bn = (tid & 31) * 2;
+  d4 cr[4][2], ci[4][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = d4{0, 0, 0, 0};
-  const int kl = lane >> 4, il = lane & 15;
-  for (int k0 = 0; k0 < kend; k0 += 4) {
-    const int k = k0 + kl;
-    double2 xa[2], qb[2];
+    for (int nb = 0; nb < 2; ++nb) cr[mb][nb] = ci[mb][nb] = d4{0, 0, 0, 0};
+  double2 pa[4], pb[2];
+  const int64_t ra = r0 + am;
+  const bool rav = ra < prow;
+  const double2* prow_p = P + (rav ? ra : 0) * (int64_t)n;
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int64_t r = rbase + a * 16 + il;
-      xa[a] = (r < prow && k < n) ? P[r * n + k] : double2{0.0, 0.0};
-      const int cj = j0 + a * 16 + il;
-      qb[a] = (k < n && cj < n) ? Q[(size_t)k * n + cj] : double2{0.0, 0.0};
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + ak + u;
+      pa[u] = (rav && k < kend) ? prow_p[k] : double2{0.0, 0.0};
     }
+    const int kb = k0 + bk;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const double nxi = -xa[a].y;
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = mfma(xa[a].x, qb[b].x, cr[a][b]);
-        cr[a][b] = mfma(nxi, qb[b].y, cr[a][b]);
-        ci[a][b] = mfma(xa[a].x, qb[b].y, ci[a][b]);
-        ci[a][b] = mfma(xa[a].y, qb[b].x, ci[a][b]);
-      }
+    for (int u = 0; u < 2; ++u) {
+      const int cj = j0 + bn + u;
+      pb[u] = (kb < kend && cj < n) ? Q[(size_t)kb * n + cj] : double2{0.0, 0.0};
     }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sm.a[buf][ak + u][am] = pa[u];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + u] = pb[u];
+  };
+  const int nst = (kend + kGK - 1) / kGK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nst;
+    if (more) gload((st + 1) * kGK);
+    gemm_stage<false>(sm, buf, wm, wn, lane, cr, ci);
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t r = rbase + a * 16 + acc_row<double>(lane, j);
-        const int cj = j0 + b * 16 + (lane & 15);
-        if (r < prow && cj < n) X[r * ldx + cj] = double2{cr[a][b][j], ci[a][b][j]};
+        const int64_t r = r0 + wm * 64 + mb * 16 + acc_row<double>(lane, j);
+        const int cj = j0 + wn * 32 + nb * 16 + (lane & 15);
+        if (r < prow && cj < n) X[r * ldx + cj] = double2{cr[mb][nb][j], ci[mb][nb][j]};
       }
 }
 
 void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n, const std::vector<cplx>& Q,
                     bool upper) {
   // panel of rows copied to scratch, then multiplied back into place
-  int64_t prow = std::max<int64_t>(64, ((int64_t)1 << 27) / ((int64_t)n * 16));   // <= 128 MiB
+  int64_t prow = std::max<int64_t>(kGM, ((int64_t)1 << 27) / ((int64_t)n * 16));   // <= 128 MiB
   prow = std::min<int64_t>(prow, rows);
-  prow = (prow + 63) / 64 * 64;
+  prow = (prow + kGM - 1) / kGM * kGM;
   c->panel.alloc((size_t)prow * n * 2 + (size_t)n * n * 2);
   double2* P = reinterpret_cast<double2*>(c->panel.ptr);
   double2* Qd = P + (size_t)prow * n;
@@ -849,10 +936,10 @@ void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n, 
   for (int64_t r0 = 0; r0 < rows; r0 += prow) {
     const int64_t pr = std::min(prow, rows - r0);
     launch_copy_rows(c, P, n, X + r0 * ldx, ldx, pr, n);
-    const int n_rb = cdiv(pr, 64), n_cb = cdiv(n, 64);
-    const int grid = 8 * cdiv((int64_t)n_rb * n_cb, 8);
+    const int n_rt = cdiv(pr, kGM), n_ct = cdiv(n, kGN);
+    const int grid = 8 * cdiv((int64_t)n_rt * n_ct, 8);
     hipLaunchKernelGGL(rotate_kernel, dim3(grid), dim3(256), 0, c->stream, P, n, pr, Qd, X + r0 * ldx, ldx,
-                       upper ? 1 : 0, n_rb, n_cb);
+                       upper ? 1 : 0, n_rt, n_ct);
     LAUNCH_CHECK();
   }
   CHFSI_HIP(hipStreamSynchronize(c->stream));   // qh leaves scope
