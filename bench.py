@@ -71,10 +71,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_operator(s, torch):
+def build_operator(s, torch, stream=None):
     import synth
     from paper_2410_02754_amd import Operator
-    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts)
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts,
+                  stream=None if stream is None else stream.cuda_stream)
     t = time.perf_counter()
     pts = op.quad_points().reshape(-1, 3)
     V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
@@ -197,7 +198,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=os.environ.get("CHFSI_BENCH_WORKLOAD", "scale"))
+    ap.add_argument("--workload", default=os.environ.get("CHFSI_BENCH_WORKLOAD", "scale"),
+                    help="scale (default), batch (k-grid + uneven systems) or adjoint")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -205,10 +207,19 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
-
     import torch
-    import synth
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        out = bench_batch(args, torch)
+    elif args.workload == "adjoint":
+        out = bench_adjoint(args, torch)
+    else:
+        out = bench_scale(args, torch)
+    print(json.dumps(out), flush=True)
+
+
+def bench_scale(args, torch):
+    import synth
     s = synth.config(args.workload)
     log(f"[bench] workload {s.name}: {s.n_cells} cells p={s.p} 2M={s.n_dof} N={s.n_vec} "
         f"block={s.block} m={s.degree} atoms={len(s.atoms)}")
@@ -316,7 +327,192 @@ def main():
         log("[bench] cpu baseline (oracle on a bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(s.name)
         out["cpu_baseline"].pop("apply_s", None)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def _task_flops(op, ik, X, W):
+    """Algorithmic flops of one H_hat application to X (cell + nonlocal stages),
+    read from the library's stage counters."""
+    op.stats_enable(True)
+    op.stats_reset()
+    op.apply_H(X, W, ik=ik)
+    st = op.stats()
+    op.stats_enable(False)
+    return st["cell_fp64"]["flops"] + st["nonlocal"]["flops"]
+
+
+def bench_batch(args, torch):
+    """The batched workload: the 8 k-points of a 2x2x2 Monkhorst-Pack grid on a
+    12^3-cell p=5 mesh (N=384) and 5 Gamma systems of 6^3..14^3 cells (N=64..320),
+    filtered (degree 16) in one persistent launch per colour phase replayed from a
+    hipGraph, tiles from the autotuner; then per-task CholGS + RR.  Timed: the
+    batched filter (FP64 and mixed) and, for reference, the same filters issued
+    task by task through chfsi_cheb_filter."""
+    import synth
+    from paper_2410_02754_amd import Batch
+    kg = synth.config("kgrid")
+    systems = [kg] + [synth.config(f"uneven{i}") for i in range(1, 6)]
+    stream = torch.cuda.Stream()            # graph capture needs a non-default stream
+    out = {}
+    with torch.cuda.stream(stream):
+        t = time.perf_counter()
+        ops = [build_operator(sy, torch, stream) for sy in systems]
+        t_setup = time.perf_counter() - t
+        tasks, meta = [], []
+        for j, sy in enumerate(systems):
+            for ik in range(len(sy.kpts)):
+                X = torch.empty((sy.n_dof, sy.n_vec), dtype=torch.complex128, device="cuda")
+                W = torch.empty_like(X)
+                ops[j].fill_random(X, sy.seed + 100 * ik, n_total_cols=sy.n_vec)
+                tasks.append((ops[j], ik, X, W))
+                meta.append((sy, j, ik))
+        # bounds per task: Lanczos upper bound, prologue CholGS + RR for a, a0
+        a, b, a0, flops = [], [], [], 0.0
+        t = time.perf_counter()
+        for (op, ik, X, W), (sy, j, _) in zip(tasks, meta):
+            v0 = torch.empty((sy.n_dof, 1), dtype=torch.complex128, device="cuda")
+            op.fill_random(v0, sy.seed + 1)
+            lo, hi = op.lanczos_bounds(v0[:, 0], 40, ik=ik)
+            op.chol_gs(X)
+            theta, _ = op.rayleigh_ritz(X, W, ik=ik)
+            a.append(float(theta[-1]))
+            a0.append(float(theta[0]))
+            b.append(hi)
+            flops += sy.degree * _task_flops(op, ik, X, W)
+        t_prologue = time.perf_counter() - t
+        X0 = [x.clone() for _, _, x, _ in tasks]
+        degree = kg.degree
+        log(f"[bench] batch: {len(tasks)} tasks, setup {t_setup:.1f} s, prologue {t_prologue:.1f} s, "
+            f"{flops / 1e12:.2f} TFLOP per batched filter")
+
+        def restore():
+            for (_, _, X, _), x0 in zip(tasks, X0):
+                X.copy_(x0)
+            torch.cuda.synchronize()
+
+        res = {}
+        for prec in (("fp64",) if args.no_mixed else ("fp64", "mixed")):
+            batch = Batch(tasks, degree, prec=prec)
+            cols, tune = batch.tiles()
+            for _ in range(max(1, args.warmup)):
+                restore()
+                batch.filter(a, b, a0)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(args.steps):
+                restore()
+                t0 = time.perf_counter()
+                batch.filter(a, b, a0)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            Yb = [x.clone() for _, _, x, _ in tasks]
+            batch.close()
+            # the same filters, task by task
+            seq = []
+            for _ in range(args.steps):
+                restore()
+                t0 = time.perf_counter()
+                for (op, ik, X, W), aa, bb, cc in zip(tasks, a, b, a0):
+                    op.cheb_filter(X, W, degree, aa, bb, cc, prec=prec, ik=ik)
+                torch.cuda.synchronize()
+                seq.append(time.perf_counter() - t0)
+            same = all(bool(torch.equal(y, x)) for y, (_, _, x, _) in zip(Yb, tasks))
+            tb, ts = float(np.median(times)), float(np.median(seq))
+            res[prec] = {"ms_per_filter": round(1e3 * tb, 2), "tflops": round(flops / tb / 1e12, 3),
+                         "sequential_ms": round(1e3 * ts, 2), "speedup_vs_sequential": round(ts / tb, 3),
+                         "bitwise_equal_to_sequential": same,
+                         "tiles_cols": cols, "autotune_ms_per_cell_stage": tune.round(4).tolist()}
+            log(f"[bench] batch {prec}: {1e3 * tb:.1f} ms per batched filter ({flops / tb / 1e12:.2f} TFLOP/s), "
+                f"task by task {1e3 * ts:.1f} ms, bitwise equal {same}")
+        # one full pass per task after the batched FP64 filter: CholGS + RR
+        restore()
+        batch = Batch(tasks, degree, prec="fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.filter(a, b, a0)
+        for (op, ik, X, W) in tasks:
+            op.chol_gs(X)
+            op.rayleigh_ritz(X, W, ik=ik)
+        torch.cuda.synchronize()
+        t_pass = time.perf_counter() - t0
+        batch.close()
+        for op in ops:
+            op.close()
+    f64 = res["fp64"]
+    out = {
+        "metric": "batched ChFSI filter TFLOP/s (8 k-points + 5 uneven Gamma systems, persistent hipGraph launch)",
+        "value": f64["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_filter"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch: 2x2x2 MP k-grid on 12^3 cells p=5 (N=384) + Gamma systems "
+                               "6^3/8^3/10^3/12^3/14^3 cells p=5 (N=64..320), degree 16",
+                   "n_tasks": len(tasks), "parallelism": "single GPU"},
+        "flops_per_batched_filter": flops,
+        "fp64": f64, "s_per_pass_batched_fp64": round(t_pass, 3),
+        "setup_s": round(t_setup, 1), "prologue_s": round(t_prologue, 1),
+    }
+    if "mixed" in res:
+        out["mixed"] = res["mixed"]
+        out["speedup_mixed_vs_fp64"] = round(f64["ms_per_filter"] / res["mixed"]["ms_per_filter"], 3)
+    return out
+
+
+def bench_adjoint(args, torch):
+    """The differentiation workload: 10^3 cells, p=5 (250k spinor dofs), N=256,
+    degree 16; forward filter and its adjoint (checkpoints every 4 steps) giving
+    dL/dX, dL/dV_eff and dL/dB_xc at the quadrature points."""
+    import synth
+    s = synth.config("adjoint")
+    op = build_operator(s, torch)
+    pts = op.quad_points().reshape(-1, 3)
+    V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+    B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+    X = torch.empty((s.n_dof, s.n_vec), dtype=torch.complex128, device="cuda")
+    op.fill_random(X, s.seed, n_total_cols=s.n_vec)
+    v0 = torch.empty((s.n_dof, 1), dtype=torch.complex128, device="cuda")
+    op.fill_random(v0, s.seed + 1)
+    lo, hi = op.lanczos_bounds(v0[:, 0], 40)
+    a, a0 = lo + 0.3 * (hi - lo), lo - 0.1
+    flops = s.degree * _task_flops(op, 0, X, torch.empty_like(X))
+    G = torch.empty_like(X)
+    op.fill_random(G, s.seed + 2, n_total_cols=s.n_vec)
+    Y, W, Xb = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
+    dV, dB = torch.zeros_like(V), torch.zeros_like(B)
+    tf, tb = [], []
+    for it in range(args.warmup + args.steps):
+        Y.copy_(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.cheb_filter(Y, W, s.degree, a, hi, a0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dV.zero_()
+        dB.zero_()
+        op.cheb_filter_backward(X, G, Xb, dV, dB, s.degree, a, hi, a0, ckpt_every=4)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it >= args.warmup:
+            tf.append(t1 - t0)
+            tb.append(t2 - t1)
+    # adjoint identity Re<G, p(H) X> = Re<p(H) G, X> as a consistency check of the timed run
+    lhs = torch.vdot(G.flatten(), Y.flatten())
+    rhs = torch.vdot(Xb.flatten(), X.flatten())
+    rel = float((lhs - rhs).abs() / lhs.abs())
+    ws = op.filter_backward_workspace(s.n_vec, s.degree, 4) if hasattr(op, "filter_backward_workspace") else None
+    op.close()
+    tfm, tbm = float(np.median(tf)), float(np.median(tb))
+    log(f"[bench] adjoint: forward {1e3 * tfm:.1f} ms, backward {1e3 * tbm:.1f} ms, identity rel {rel:.1e}")
+    return {
+        "metric": "Chebyshev filter adjoint: dL/dX, dL/dV_eff, dL/dB_xc (checkpoints every 4 steps)",
+        "value": round(1e3 * tbm, 2), "unit": "ms per backward", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * (tfm + tbm), 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint: 10^3 cells p=5 (250000 spinor dofs), 8 atoms l<=1, N=256, degree 16",
+                   "parallelism": "single GPU"},
+        "forward_ms": round(1e3 * tfm, 2), "forward_tflops": round(flops / tfm / 1e12, 3),
+        "backward_over_forward": round(tbm / tfm, 3), "adjoint_identity_rel": rel,
+        "workspace": ws,
+    }
 
 
 if __name__ == "__main__":

@@ -214,6 +214,9 @@ def config(name: str) -> System:
     scale   : 20^3 cells, p=6, L=24, Gamma, 200 Gaussians, 64 atoms (l<=2), N=512 (4x128), m=24, 4 passes
     reduced : 6^3 cells, p=6, h=1.2 with the same generator densities as `scale`, N=128, m=24
     kgrid   : 12^3 cells, p=5, L=14.4, 2x2x2 Monkhorst-Pack, 27 atoms (l<=1), N=384, m=16
+    uneven1..uneven5 : Gamma systems of 6^3, 8^3, 10^3, 12^3, 14^3 cells, p=5, h=1.2, Gaussians
+              at 6/512 per bohr^3, ceil(E/32) atoms (l<=1), N=64, 128, 192, 256, 320, m=16,
+              seeds 1..5 (the uneven members of the batched workload)
     adjoint : 10^3 cells, p=5, L=12, Gamma, 8 atoms (l<=1), N=256, m=16
     """
     if name == "tiny":
@@ -234,6 +237,14 @@ def config(name: str) -> System:
                            n_gauss=round(6 / 512 * L ** 3), n_atoms=27, atom_lattice=3,
                            lmax=1, rcut_sigmas=6.0, n_vec=384, block=128, degree=16,
                            passes=3, seed=1)
+    if name.startswith("uneven") and name[6:].isdigit() and 1 <= int(name[6:]) <= 5:
+        i = int(name[6:])
+        nc = 4 + 2 * i
+        L = 1.2 * nc
+        return make_system(name, n_cells=(nc, nc, nc), box=(L, L, L), p=5,
+                           n_gauss=max(1, round(6 / 512 * L ** 3)), n_atoms=-(-nc ** 3 // 32),
+                           lmax=1, rcut_sigmas=6.0, n_vec=64 * i, block=64 * i, degree=16,
+                           passes=3, seed=i)
     if name == "adjoint":
         return make_system("adjoint", n_cells=(10, 10, 10), box=(12.0, 12.0, 12.0), p=5,
                            n_gauss=round(6 / 512 * 12.0 ** 3), n_atoms=8, lmax=1,
