@@ -204,6 +204,41 @@ def test_full_passes_tiny():
     op.close()
 
 
+def test_full_passes_p6_degree24():
+    """Two ChFSI passes at the large workload's element order, mesh size and
+    filter degree (p=6, h=1.2 bohr, m=24) on a 2x2x3-cell periodic piece (even and
+    odd colourings) with an l<=2 atom whose support wraps the box, N=64 in two
+    blocks of 32 with shared bounds: Ritz values to 1e-10 Ha, spans of
+    gap-separated clusters."""
+    s = synth.make_system("p6m24", n_cells=(2, 2, 3), box=(2.4, 2.4, 3.6), p=6, n_gauss=3, n_atoms=1,
+                          lmax=2, rcut_sigmas=6.0, n_vec=64, block=32, degree=24, passes=2, seed=4)
+    H = _oracle(s)
+    op = _op(s)
+    X0 = synth.start_block(s, s.n_dof)
+    _, b = och.lanczos_bounds(H, synth.lanczos_start(s, s.n_dof), 40)
+    hist = []
+    tho, Xo, ro = och.run(H, X0, s.degree, s.passes, s.block, b, hist)
+    X = torch.tensor(X0, device="cuda")
+    W = torch.empty_like(X)
+    op.chol_gs(X)
+    th, r = op.rayleigh_ritz(X, W)
+    for p in range(s.passes):
+        a, a0 = float(th[-1]), float(th[0])
+        for c0 in range(0, s.n_vec, s.block):
+            op.cheb_filter(X[:, c0:c0 + s.block], W[:, :s.block], s.degree, a, b, a0)
+        op.chol_gs(X)
+        th, r = op.rayleigh_ritz(X, W)
+        _say(f"[passes p6] pass {p + 1}: max |dtheta| = {np.abs(th - hist[p + 1][0]).max():.3e}")
+    assert np.abs(th - tho).max() < 1e-10
+    assert np.abs(r - ro).max() < 1e-8
+    Xg = X.cpu().numpy()
+    gaps = np.where(np.diff(tho) > 1e-6)[0]
+    edges = [0] + list(gaps + 1) + [len(tho)]
+    for i0, i1 in zip(edges[:-1], edges[1:]):
+        assert och.sin_largest_angle(Xg[:, i0:i1], Xo[:, i0:i1]) < 1e-8
+    op.close()
+
+
 def test_fill_random_bit_exact():
     s = SYSTEMS["tiny"]()
     from paper_2410_02754_amd import Operator

@@ -79,7 +79,7 @@ def _sample_nodes(s, rng, n_near=48, n_far=16):
     corners of the box, so different cells and colours)."""
     from oracle.fe import Mesh
     mesh = Mesh(s.n_cells, s.box, s.p, s.quad, s.n_q)
-    cand = rng.choice(s.n_nodes, 400000, replace=False)
+    cand = rng.choice(s.n_nodes, min(400000, s.n_nodes), replace=False)
     Nx, Ny, _ = mesh.N
     idx = np.stack([cand % Nx, (cand // Nx) % Ny, cand // (Nx * Ny)], axis=1)
     xyz = np.stack([(idx[:, d] // s.p) * mesh.h[d] + (mesh.xi[idx[:, d] % s.p] + 1) * mesh.h[d] / 2
