@@ -252,10 +252,10 @@ def bench_scale(args, torch):
     cell_ms = fst["cell_ms"] / max(1, fst["cell_launches"])
     achieved = cell_per_launch / (cell_ms * 1e-3) / 1e12 if cell_ms > 0 else 0.0
     exec_tf = fst["cell_exec"] / (fst["cell_ms"] * 1e-3) / 1e12 if fst["cell_ms"] > 0 else 0.0
-    # filter launches: one colour of cells x row tiles x column tiles of 128
+    # filter launches: one colour of cells x row tiles x column tiles of 64
     n_colour_cells = int(np.prod(s.n_cells)) // 8
     nloc = (s.p + 1) ** 3
-    grid_wg = n_colour_cells * (((nloc + 15) // 16 + 1) // 2) * ((s.block + 127) // 128)
+    grid_wg = n_colour_cells * (((nloc + 15) // 16 + 1) // 2) * ((s.block + 63) // 64)
     traffic = measured_traffic(grid_wg)
 
     out = {
@@ -276,7 +276,7 @@ def bench_scale(args, torch):
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_bytes_per_launch": cell_alg_bytes(s),
-                     "kernel": "cell_apply_kernel<double> (gather + Pauli-form cell products + scatter-add)",
+                     "kernel": "cell_apply_kernel<double, 2, false> (gather + Pauli-form cell products + scatter-add, 64-column tiles)",
                      "flops_per_launch": cell_per_launch, "mean_launch_ms": round(cell_ms, 4),
                      "executed_mfma_tflops": round(exec_tf, 3),
                      "executed_frac": round(exec_tf / PEAK_FP64, 4)},
