@@ -493,6 +493,7 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
   nl.max_pj = 1;
   nl.n_chunks = 0;
   nl.n_pairs = 0;
+  nl.real_proj = false;
   if (n_atoms == 0) return;
   std::vector<AtomWork> work(n_atoms);
   parallel_for(n_atoms, [&](int a) { atom_tables(c, kp.k, atoms[a], work[a]); });
@@ -508,6 +509,13 @@ void build_nonlocal(chfsi_ctx* c, KPoint& kp, int n_atoms, const chfsi_atom_desc
     nl.atoms[a].delta = work[a].delta;
   }
   nl.n_entries = atom_off[n_atoms];
+  nl.real_proj = true;
+  for (int a = 0; a < n_atoms && nl.real_proj; ++a)
+    for (const cplx& v : work[a].P)
+      if (v.imag() != 0.0) {
+        nl.real_proj = false;
+        break;
+      }
   std::vector<int32_t> sup(nl.n_entries);
   std::vector<double2> proj((size_t)nl.n_entries * mp, double2{0.0, 0.0});
   std::vector<float2> proj32((size_t)nl.n_entries * mp, float2{0.0f, 0.0f});

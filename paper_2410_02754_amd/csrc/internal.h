@@ -101,6 +101,7 @@ struct NonlocalK {
   DevBuf<double2> delta;        // [n_atoms][2 max_pj][2 max_pj]
   DevBuf<int32_t> atom_off;     // [n_atoms + 1] entry offsets
   DevBuf<int32_t> atom_npj;     // [n_atoms]
+  bool real_proj = false;       // every projector value is real (Gamma point)
   // chunked reduction work list for C = P^H X: the entries of one atom inside one
   // window of kNlWindow consecutive global nodes (at most kNlChunk of them);
   // chunk ids are grouped by atom (the reduction order), chunk_order lists them

@@ -89,12 +89,18 @@ template <> struct C2<float> { typedef float2 type; };
 
 constexpr int kMaxPj = 9;
 
-// Contraction partials, one wave per (chunk of an atom's support, 32-column
-// tile): partial[chunk][2 chi + s][n] = sum_j conj(P[j][chi]) X[2 node_j + s][n].
+// 16-column blocks per wave of the contraction and initialisation kernels: one
+// in FP64 (fewer registers, more resident waves to cover the row loads), two in FP32.
+template <class T>
+constexpr int nl_col_blocks() { return sizeof(T) == 8 ? 1 : 2; }
+
+// Contraction partials, one wave per (chunk of an atom's support, 16- or
+// 32-column tile): partial[chunk][2 chi + s][n] = sum_j conj(P[j][chi]) X[2 node_j + s][n].
 // Done as 16x16x4 MFMAs: row = projector index chi (n_pj <= 9 of the 16 rows
 // used), k = four support entries per step, column = 16 of the tile's columns;
 // sixteen entries' operands are loaded before their MFMAs are issued.
-template <class T>
+// REALP: the projector values are real (Gamma point), two real MFMAs per step.
+template <class T, bool REALP>
 __global__ __launch_bounds__(256) void nl_contract_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ sup_node,
     const int32_t* __restrict__ chunk_atom, const int32_t* __restrict__ chunk_begin,
@@ -104,6 +110,7 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
   typedef typename C2<T>::type CT;
   typedef typename Vec4<T>::type V4;
   constexpr int U = 4;                    // k-steps per batch
+  constexpr int NCB = nl_col_blocks<T>();
   // each XCD takes a contiguous range of the (window, atom)-ordered chunks, so the
   // chunks of different atoms over the same rows meet in that XCD's L2
   const int per_xcd = (int)((gridDim.x + 7) / 8);
@@ -117,22 +124,22 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
   const int a = chunk_atom[ch], b = chunk_begin[ch], e = chunk_end[ch];
   const int npj = atom_npj[a];
   const bool rv = il < npj;               // this lane's A row is a projector in use
-  int col[2];
-  bool cv[2];
+  int col[NCB];
+  bool cv[NCB];
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    col[cb] = ct * 32 + cb * 16 + il;
+  for (int cb = 0; cb < NCB; ++cb) {
+    col[cb] = ct * 16 * NCB + cb * 16 + il;
     cv[cb] = col[cb] < n_vec;
     if (!cv[cb]) col[cb] = n_vec - 1;     // clamped: loads stay in bounds
   }
-  V4 cr[2][2], ci[2][2];                  // [spin][16-column block]
+  V4 cr[2][NCB], ci[2][NCB];              // [spin][16-column block]
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) cr[sp][cb] = ci[sp][cb] = V4{0, 0, 0, 0};
+    for (int cb = 0; cb < NCB; ++cb) cr[sp][cb] = ci[sp][cb] = V4{0, 0, 0, 0};
   for (int j0 = b; j0 < e; j0 += 4 * U) {
     CT pv[U];
-    double2 xv[U][2][2];
+    double2 xv[U][2][NCB];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = j0 + 4 * u + kl;      // entry of this lane's k index
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < NCB; ++cb) {
           const double2 v = X[(2 * nd + sp) * ldx + col[cb]];
           xv[u][sp][cb] = (jv && cv[cb]) ? v : double2{0.0, 0.0};
         }
@@ -153,12 +160,12 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < NCB; ++cb) {
           const T xr = (T)xv[u][sp][cb].x, xi = (T)xv[u][sp][cb].y;
           cr[sp][cb] = mfma(pr, xr, cr[sp][cb]);      // conj(p) x
-          cr[sp][cb] = mfma(pi, xi, cr[sp][cb]);
+          if (!REALP) cr[sp][cb] = mfma(pi, xi, cr[sp][cb]);
           ci[sp][cb] = mfma(pr, xi, ci[sp][cb]);
-          ci[sp][cb] = mfma(npi, xr, ci[sp][cb]);
+          if (!REALP) ci[sp][cb] = mfma(npi, xr, ci[sp][cb]);
         }
     }
   }
@@ -168,7 +175,7 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
     const int x = acc_row<T>(lane, j);
     if (x >= npj) continue;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < NCB; ++cb) {
       if (!cv[cb]) continue;
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) {
@@ -255,19 +262,20 @@ __global__ __launch_bounds__(64) void nl_delta_kernel(const typename C2<T>::type
 }
 
 // Recurrence initialisation fused with the nonlocal back-product, one wave per
-// (run of kNlRun = 16 consecutive global nodes, 32-column tile):
+// (run of kNlRun = 16 consecutive global nodes, 16- or 32-column tile):
 //   W[2I+s][n] = beta Wold[2I+s][n] + gamma X[2I+s][n] + rscale[n] Rs[2I+s][n]
 //               + sum_{atoms a at I} sum_chi P[entry(a, I)][chi] C'[a][2 chi + s][n]
 // For each atom meeting the run, the back-product is the complex product of the
-// run's 16 x n_pj projector block with the n_pj x 32 coefficient tile, done as
+// run's 16 x n_pj projector block with the n_pj x (16 | 32) coefficient tile, done as
 // 16x16x4 MFMAs (k = projector index, padded to a multiple of 4; nodes of the run
 // outside the atom's support contribute zero rows).  All operands of an atom are
 // loaded before its MFMAs; each coefficient row is read once per run.  W and
 // Wold are not read without the beta term, X without the gamma term, Rs without
-// the residual term (FL: which terms are present).
+// the residual term (FL: which terms are present).  REALP: real projector values
+// (Gamma point), two real MFMAs per step instead of four.
 constexpr int kInitBeta = 1, kInitGamma = 2, kInitRs = 4;
 
-template <class T, int FL>
+template <class T, int FL, bool REALP>
 __global__ __launch_bounds__(256) void init_nl_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ run_off,
     const int32_t* __restrict__ pair_atom, const int32_t* __restrict__ pair_ent,
@@ -280,24 +288,25 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
   typedef typename Vec4<T>::type V4;
   static_assert(kNlRun == 16, "one MFMA row block per run");
   constexpr int KS = (kMaxPj + 3) / 4;    // k-steps per atom
+  constexpr int NCB = nl_col_blocks<T>();
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   if (wid >= n_work) return;              // no barrier in this kernel
   const int run = wid / n_coltiles, ct = wid - run * n_coltiles;
   const int lane = threadIdx.x & 63;
   const int kl = lane >> 4, il = lane & 15;
-  int col[2];
-  bool cv[2];
+  int col[NCB];
+  bool cv[NCB];
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    col[cb] = ct * 32 + cb * 16 + il;
+  for (int cb = 0; cb < NCB; ++cb) {
+    col[cb] = ct * 16 * NCB + cb * 16 + il;
     cv[cb] = col[cb] < n_vec;
     if (!cv[cb]) col[cb] = n_vec - 1;     // clamped: loads stay in bounds
   }
-  V4 dr[2][2], di[2][2];                  // [spin][16-column block]
+  V4 dr[2][NCB], di[2][NCB];              // [spin][16-column block]
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) dr[sp][cb] = di[sp][cb] = V4{0, 0, 0, 0};
+    for (int cb = 0; cb < NCB; ++cb) dr[sp][cb] = di[sp][cb] = V4{0, 0, 0, 0};
   if (has_nl) {
     const int p0 = run_off[run], p1 = run_off[run + 1];
     for (int pr = p0; pr < p1; ++pr) {
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
       const int ent = pair_ent[(size_t)pr * kNlRun + il];      // A row = node il of the run
       const CT* cpa = Cp + (size_t)a * 2 * max_pj * n_vec;
       CT pa[KS];
-      CT bv[KS][2][2];
+      CT bv[KS][2][NCB];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int x = 4 * ks + kl;                               // projector index of this lane
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) {
+          for (int cb = 0; cb < NCB; ++cb) {
             const CT v = cpa[(size_t)(2 * xr + sp) * n_vec + col[cb]];
             bv[ks][sp][cb] = (xv && cv[cb]) ? v : CT{(T)0, (T)0};
           }
@@ -328,11 +337,11 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) {
+          for (int cb = 0; cb < NCB; ++cb) {
             dr[sp][cb] = mfma(pa[ks].x, bv[ks][sp][cb].x, dr[sp][cb]);
-            dr[sp][cb] = mfma(nai, bv[ks][sp][cb].y, dr[sp][cb]);
+            if (!REALP) dr[sp][cb] = mfma(nai, bv[ks][sp][cb].y, dr[sp][cb]);
             di[sp][cb] = mfma(pa[ks].x, bv[ks][sp][cb].y, di[sp][cb]);
-            di[sp][cb] = mfma(pa[ks].y, bv[ks][sp][cb].x, di[sp][cb]);
+            if (!REALP) di[sp][cb] = mfma(pa[ks].y, bv[ks][sp][cb].x, di[sp][cb]);
           }
       }
     }
@@ -346,9 +355,9 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
     const int64_t node = node0 + acc_row<T>(lane, j);
     const bool nv = node < n_nodes;
     const int64_t nodec = nv ? node : n_nodes - 1;
-    double2 v[2][2];
+    double2 v[NCB][2];
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) {
         const int64_t row = 2 * nodec + sp;
@@ -373,7 +382,7 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
         v[cb][sp] = t;
       }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp)
         if (nv && cv[cb]) W[(2 * node + sp) * ldw + col[cb]] = v[cb][sp];
@@ -402,11 +411,17 @@ static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
   const double nl_bytes = (double)nl.n_entries * (2.0 * n_vec * sizeof(double2) + nl.max_pj * sizeof(CT));
   StageTimer tm(c, CHFSI_STAGE_NONLOCAL, nl_flops, nl_flops, nl_bytes);
   const int nct = cdiv(n_vec, 64);
-  const int nct32 = cdiv(n_vec, 32);
+  const int nct32 = cdiv(n_vec, 16 * nl_col_blocks<T>());
   const int n_work = nl.n_chunks * nct32;
-  hipLaunchKernelGGL(nl_contract_kernel<T>, dim3(8 * cdiv(cdiv(n_work, 4), 8)), dim3(256), 0, c->stream, proj,
-                     nl.sup_node.ptr, nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr,
-                     nl.chunk_order.ptr, nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X, ldx, n_vec, partial);
+  const dim3 cgrid(8 * cdiv(cdiv(n_work, 4), 8));
+  if (nl.real_proj)
+    hipLaunchKernelGGL((nl_contract_kernel<T, true>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
+                       nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
+                       nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X, ldx, n_vec, partial);
+  else
+    hipLaunchKernelGGL((nl_contract_kernel<T, false>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
+                       nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
+                       nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X, ldx, n_vec, partial);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(nl_reduce_kernel<T>, dim3(nl.n_atoms, mr, nct), dim3(64), 0, c->stream, partial,
                      nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.max_pj, n_vec, Csum);
@@ -428,7 +443,7 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
                 (double)rows * n_vec * sizeof(double2) * (1.0 + (beta != 0.0) + (gamma != 0.0)));
   const int has = Cp != nullptr;
   const int64_t n_runs = (c->n_nodes + kNlRun - 1) / kNlRun;
-  const int nct = cdiv(n_vec, 32);
+  const int nct = cdiv(n_vec, 16 * nl_col_blocks<T>());
   const int n_work = (int)(n_runs * nct);
   const int fl = (beta != 0.0 ? kInitBeta : 0) | (gamma != 0.0 ? kInitGamma : 0) | (Rs ? kInitRs : 0);
   const dim3 grid(cdiv(n_work, 4)), blk(256);
@@ -436,16 +451,25 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
   proj, has ? nl.run_off.ptr : nullptr, has ? nl.pair_atom.ptr : nullptr, has ? nl.pair_ent.ptr : nullptr, \
       has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has, X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale,    \
       c->n_nodes, n_work, nct, n_vec, beta, gamma
+#define INIT_NL_CASE(F)                                                                        \
+  case F:                                                                                      \
+    if (has && nl.real_proj)                                                                   \
+      hipLaunchKernelGGL((init_nl_kernel<T, F, true>), grid, blk, 0, c->stream, INIT_NL_ARGS);  \
+    else                                                                                       \
+      hipLaunchKernelGGL((init_nl_kernel<T, F, false>), grid, blk, 0, c->stream, INIT_NL_ARGS); \
+    break;
   switch (fl) {
-    case 0: hipLaunchKernelGGL((init_nl_kernel<T, 0>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    case 1: hipLaunchKernelGGL((init_nl_kernel<T, 1>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    case 2: hipLaunchKernelGGL((init_nl_kernel<T, 2>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    case 3: hipLaunchKernelGGL((init_nl_kernel<T, 3>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    case 4: hipLaunchKernelGGL((init_nl_kernel<T, 4>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    case 5: hipLaunchKernelGGL((init_nl_kernel<T, 5>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    case 6: hipLaunchKernelGGL((init_nl_kernel<T, 6>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
-    default: hipLaunchKernelGGL((init_nl_kernel<T, 7>), grid, blk, 0, c->stream, INIT_NL_ARGS); break;
+    INIT_NL_CASE(0)
+    INIT_NL_CASE(1)
+    INIT_NL_CASE(2)
+    INIT_NL_CASE(3)
+    INIT_NL_CASE(4)
+    INIT_NL_CASE(5)
+    INIT_NL_CASE(6)
+    default:
+    INIT_NL_CASE(7)
   }
+#undef INIT_NL_CASE
 #undef INIT_NL_ARGS
   LAUNCH_CHECK();
 }
