@@ -20,6 +20,8 @@ using namespace chfsi;
 struct BatchGroup {
   int cb;
   bool has_s;
+  int chunk;                                 // tasks [chunk * kBatchLaunchTasks, +kBatchLaunchTasks)
+  BatchTaskArgs args;                        // their descriptors, by value for the launch
   std::vector<int> n_items;                  // per colour
   std::vector<DevBuf<int4>*> items;          // per colour
   int grid[2];                               // persistent grid: [0] FP32, [1] FP64
@@ -37,7 +39,6 @@ struct chfsi_batch {
   std::vector<double> tune_ms;               // [n_tasks][3] timings of CB = 1, 2, 4 (or -1)
   std::vector<BatchGroup*> groups;
   int max_colours = 0;
-  DevBuf<BatchTaskDev> dtasks;
   DevBuf<double> alpha_tab;                  // [degree][n_tasks]
   std::vector<double> bounds;                // bounds the graph was captured with
   hipGraph_t graph = nullptr;
@@ -52,15 +53,17 @@ struct chfsi_batch {
 
 static int cb_index(int cb) { return cb == 4 ? 2 : cb == 2 ? 1 : 0; }
 
-// item lists of one (CB, k-term) group, one list per colour, in XCD order
+// item lists of one (CB, k-term, task chunk) group, one list per colour, in XCD
+// order; item task indices are local to the chunk
 static void build_items(chfsi_batch* b, BatchGroup& g) {
   const int nt = (int)b->tasks.size();
+  const int t0 = g.chunk * kBatchLaunchTasks, t1 = std::min(nt, t0 + kBatchLaunchTasks);
   g.n_items.assign(b->max_colours, 0);
   g.items.assign(b->max_colours, nullptr);
   for (int col = 0; col < b->max_colours; ++col) {
     std::vector<std::vector<int4>> per_xcd(8);
     int unit = 0;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = t0; t < t1; ++t) {
       if (b->cb[t] != g.cb || (!b->kps[t]->gamma) != g.has_s) continue;
       chfsi_ctx* c = b->tasks[t].ctx;
       if (col >= c->n_colours) continue;
@@ -72,7 +75,7 @@ static void build_items(chfsi_batch* b, BatchGroup& g) {
       const int nct = (b->tasks[t].n_vec + 32 * g.cb - 1) / (32 * g.cb);
       for (int e : cells)
         for (int ct = 0; ct < nct; ++ct, ++unit)
-          for (int rt = 0; rt < nrt; ++rt) per_xcd[unit % 8].push_back(int4{t, e, rt, ct});
+          for (int rt = 0; rt < nrt; ++rt) per_xcd[unit % 8].push_back(int4{t - t0, e, rt, ct});
     }
     size_t len = 0;
     for (auto& v : per_xcd) len = std::max(len, v.size());
@@ -130,8 +133,9 @@ static void run_filter(chfsi_batch* b, const std::vector<double>& bounds) {
     for (int col = 0; col < b->max_colours; ++col)
       for (auto* g : b->groups) {
         if (g->n_items[col] == 0) continue;
-        launch_cell_batch(b->stream, prec == CHFSI_PREC_FP64, g->cb, g->has_s, b->dtasks.ptr, g->items[col]->ptr,
-                          g->n_items[col], b->alpha_tab.ptr + (size_t)(k - 1) * nt, src, g->grid[prec == CHFSI_PREC_FP64]);
+        launch_cell_batch(b->stream, prec == CHFSI_PREC_FP64, g->cb, g->has_s, g->args, g->items[col]->ptr,
+                          g->n_items[col], b->alpha_tab.ptr + (size_t)(k - 1) * nt + g->chunk * kBatchLaunchTasks,
+                          src, g->grid[prec == CHFSI_PREC_FP64]);
       }
   }
   if (m & 1)
@@ -203,26 +207,29 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
       const int widest = tk.n_vec > 64 ? 4 : tk.n_vec > 32 ? 2 : 1;
       b->cb[t] = widest;
       if (!(flags & CHFSI_BATCH_AUTOTUNE)) continue;
+      // fastest candidate; a narrower tile must win by more than 1 % (it costs more
+      // operator reads per column)
       double best = 1e300;
-      for (int cb : {1, 2, 4}) {
+      for (int cb : {4, 2, 1}) {
         if (cb > widest) continue;
         const double ms = time_cell_stage(tk.ctx, *b->kps[t], cb, tprec, (const double2*)tk.X_d, tk.ldx,
                                           (double2*)tk.work_d, tk.ldw, tk.n_vec, 2);
         b->tune_ms[(size_t)t * 3 + cb_index(cb)] = ms;
-        if (ms < best * 0.98) {
+        if (ms < best * 0.99) {
           best = ms;
           b->cb[t] = cb;
         }
       }
     }
-    std::map<std::pair<int, bool>, int> gid;
+    std::map<std::tuple<int, int, bool>, int> gid;
     for (int t = 0; t < n_tasks; ++t) {
-      auto key = std::make_pair(b->cb[t], !b->kps[t]->gamma);
+      auto key = std::make_tuple(t / kBatchLaunchTasks, b->cb[t], !b->kps[t]->gamma);
       if (!gid.count(key)) {
         gid[key] = (int)b->groups.size();
         auto* g = new BatchGroup();
-        g->cb = key.first;
-        g->has_s = key.second;
+        g->chunk = std::get<0>(key);
+        g->cb = std::get<1>(key);
+        g->has_s = std::get<2>(key);
         b->groups.push_back(g);
       }
     }
@@ -247,7 +254,11 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
       dt[t].pad = 0;
       nonlocal_prepare(c, kp, tk.n_vec);
     }
-    b->dtasks.upload(dt.data(), dt.size(), b->stream);
+    for (auto* g : b->groups) {
+      g->args = BatchTaskArgs{};
+      for (int j = 0; j < kBatchLaunchTasks && g->chunk * kBatchLaunchTasks + j < n_tasks; ++j)
+        g->args.t[j] = dt[g->chunk * kBatchLaunchTasks + j];
+    }
     b->alpha_tab.alloc((size_t)degree * n_tasks);
     CHFSI_HIP(hipStreamSynchronize(b->stream));
     *out = b;

@@ -335,15 +335,20 @@ __global__ __launch_bounds__(256) void cell_apply_kernel(
 // operators (k-points, systems).  Items were ordered on the host so that item
 // i runs on XCD i % 8 and the row tiles of a cell share an XCD.
 
+// Resident workgroups per CU the persistent form is compiled for: what the
+// per-colour kernel reaches, so the item walk costs no occupancy.
+template <int CB>
+constexpr int cell_min_blocks() { return CB == 4 ? 1 : CB == 2 ? 3 : 4; }
+
 template <class T, int CB, bool HAS_S>
-__global__ __launch_bounds__(256) void cell_batch_kernel(const BatchTaskDev* __restrict__ tasks,
+__global__ __launch_bounds__(256, cell_min_blocks<CB>()) void cell_batch_kernel(const BatchTaskArgs tasks,
                                                          const int4* __restrict__ items, int n_items,
                                                          const double* __restrict__ alpha, int src) {
   __shared__ CellSmem<T, CB> sm;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int4 w = items[it];
     if (w.x < 0) continue;                // padding item (uniform over the block)
-    const BatchTaskDev& t = tasks[w.x];
+    const BatchTaskDev& t = tasks.t[w.x];
     const T* cm = sizeof(T) == 8 ? (const T*)t.cm64 : (const T*)t.cm32;
     cell_tile<T, CB, HAS_S>(sm, cm, t.cell_nodes, w.y, w.z, w.w, t.nloc, t.nrb, t.nkb, t.nmat, t.buf[src],
                             t.ld[src], t.buf[src ^ 1], t.ld[src ^ 1], t.n_vec, alpha[w.x]);
@@ -404,7 +409,7 @@ void launch_cell_products(chfsi_ctx* c, KPoint& kp, int prec, const double2* X, 
 
 // ---------------------------------------------------------------- batched form
 template <class T, int CB, bool HAS_S>
-static void launch_batch_t(hipStream_t s, const BatchTaskDev* tasks, const int4* items, int n_items,
+static void launch_batch_t(hipStream_t s, const BatchTaskArgs& tasks, const int4* items, int n_items,
                            const double* alpha, int src, int grid) {
   hipLaunchKernelGGL((cell_batch_kernel<T, CB, HAS_S>), dim3(grid), dim3(256), 0, s, tasks, items, n_items, alpha,
                      src);
@@ -412,7 +417,7 @@ static void launch_batch_t(hipStream_t s, const BatchTaskDev* tasks, const int4*
 }
 
 template <class T, bool HAS_S>
-static void launch_batch_cb(hipStream_t s, int CB, const BatchTaskDev* tasks, const int4* items, int n_items,
+static void launch_batch_cb(hipStream_t s, int CB, const BatchTaskArgs& tasks, const int4* items, int n_items,
                             const double* alpha, int src, int grid) {
   if (CB == 4)
     launch_batch_t<T, 4, HAS_S>(s, tasks, items, n_items, alpha, src, grid);
@@ -422,7 +427,7 @@ static void launch_batch_cb(hipStream_t s, int CB, const BatchTaskDev* tasks, co
     launch_batch_t<T, 1, HAS_S>(s, tasks, items, n_items, alpha, src, grid);
 }
 
-void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const BatchTaskDev* tasks, const int4* items,
+void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const BatchTaskArgs& tasks, const int4* items,
                        int n_items, const double* alpha, int src, int grid) {
   if (fp64) {
     if (has_s) launch_batch_cb<double, true>(s, CB, tasks, items, n_items, alpha, src, grid);

@@ -144,6 +144,13 @@ struct BatchTaskDev {
   int n_vec, nloc, nrb, nkb, nmat;
   int pad;
 };
+// Task descriptors of one persistent launch, passed by value in the kernel
+// arguments (pointers read from the argument segment compile to global, not
+// flat, accesses); larger batches launch in chunks of this many tasks.
+constexpr int kBatchLaunchTasks = 32;
+struct BatchTaskArgs {
+  BatchTaskDev t[kBatchLaunchTasks];
+};
 
 struct StageRec {
   int stage;
@@ -252,7 +259,7 @@ void column_resid_norms(chfsi_ctx* c, const double2* W, int64_t ldw, const doubl
                         int64_t rows, int n, const double* theta, double* out);
 double dot_re(chfsi_ctx* c, const double2* x, const double2* y, int64_t rows);
 // batched filter support (kernels.hip)
-void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const BatchTaskDev* tasks, const int4* items,
+void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const BatchTaskArgs& tasks, const int4* items,
                        int n_items, const double* alpha, int src, int grid);
 int cell_batch_blocks_per_cu(bool fp64, int CB, bool has_s);
 double time_cell_stage(chfsi_ctx* c, KPoint& kp, int CB, int prec, const double2* X, int64_t ldx, double2* W,
