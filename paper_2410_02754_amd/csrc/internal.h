@@ -190,6 +190,8 @@ struct chfsi_ctx {
   // internal scratch
   chfsi::DevBuf<double> scratch;              // reductions, small matrices
   chfsi::DevBuf<double> panel;                // row panel for in-place rotations
+  chfsi::DevBuf<double> cd_partial;           // adjoint cross densities per column group
+  chfsi::DevBuf<double> ref_b1, ref_wq;       // 1-D interpolation table and weights (device copy)
   // stage timing
   bool stats_on = false;
   std::vector<chfsi::StageRec> pending;

@@ -546,35 +546,39 @@ void nonlocal_prepare(chfsi_ctx* c, KPoint& kp, int n_vec) {
 // ============================================================================
 // Adjoint: fields at the quadrature points and their cross densities
 // ============================================================================
-// One block per cell.  For CC columns at a time, the M^{-1/2}-scaled cell rows
-// of L and Y (both spins) are gathered into LDS and interpolated to the
-// quadrature points by sum factorisation over x, y, z (N_i = l_ax l_ay l_az);
-// each thread then owns up to four points and accumulates, over all columns,
-//   Re l^H y,  Re l^H sigma_x y,  Re l^H sigma_y y,  Re l^H sigma_z y.
+// One block per (cell, group of columns).  For CC columns at a time, the
+// M^{-1/2}-scaled cell rows of L and Y (both spins) are gathered into LDS and
+// interpolated to the quadrature points by sum factorisation over x, y, z
+// (N_i = l_ax l_ay l_az); each thread then owns up to four points and
+// accumulates, over the group's columns,
+//   Re l^H y,  Re l^H sigma_x y,  Re l^H sigma_y y,  Re l^H sigma_z y,
+// written (times w_q J) to partial[group][cell][point][4]; a second kernel adds
+// the groups in a fixed order into dV, dB.
 constexpr int kCdMaxQ = 4;   // points per thread: nq^3 <= 1024
 __global__ __launch_bounds__(256) void cross_density_kernel(
     const double2* __restrict__ L, int64_t ldl, const double2* __restrict__ Y, int64_t ldy, int n_vec,
     const int32_t* __restrict__ cell_nodes, const double* __restrict__ minv_sqrt,
     const double* __restrict__ B1, const double* __restrict__ wq1, double J, int np1, int nq, int nloc,
-    int maxsz, int CC, double alpha, double* __restrict__ dV, double* __restrict__ dB) {
+    int maxsz, int CC, int cols_per_group, double* __restrict__ partial) {
   extern __shared__ double2 sm[];
   double2* bufA = sm;                               // [CC*4][maxsz]
   double2* bufB = sm + (size_t)CC * 4 * maxsz;      // [CC*4][maxsz]
   double* sBt = reinterpret_cast<double*>(bufB + (size_t)CC * 4 * maxsz);   // [np1][nq]
-  const int e = blockIdx.x, tid = threadIdx.x;
+  const int e = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
   const int nq3 = nq * nq * nq;
+  const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
   for (int t = tid; t < np1 * nq; t += 256) sBt[t] = B1[t];
   double acc[kCdMaxQ][4];
 #pragma unroll
   for (int i = 0; i < kCdMaxQ; ++i) acc[i][0] = acc[i][1] = acc[i][2] = acc[i][3] = 0.0;
   const int32_t* nodes = cell_nodes + (size_t)e * nloc;
-  for (int n0 = 0; n0 < n_vec; n0 += CC) {
+  for (int n0 = c_begin; n0 < c_end; n0 += CC) {
     // gather: stream s = 2 * operand + spin
     for (int t = tid; t < CC * 4 * nloc; t += 256) {
       const int i = t % nloc, s = (t / nloc) % 4, cc = t / (4 * nloc);
       const int col = n0 + cc;
       double2 v = {0.0, 0.0};
-      if (col < n_vec) {
+      if (col < c_end) {
         const int64_t I = nodes[i];
         const int64_t r = 2 * I + (s & 1);
         const double sc = minv_sqrt[I];
@@ -656,12 +660,25 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
     const int q = tid + 256 * qi;
     if (q >= nq3) continue;
     const int qx = q % nq, qy = (q / nq) % nq, qz = q / (nq * nq);
-    const double w = alpha * wq1[qx] * wq1[qy] * wq1[qz] * J;
-    const size_t eq = (size_t)e * nq3 + q;
-    dV[eq] += w * acc[qi][0];
-    dB[eq * 3 + 0] += w * acc[qi][1];
-    dB[eq * 3 + 1] += w * acc[qi][2];
-    dB[eq * 3 + 2] += w * acc[qi][3];
+    const double w = wq1[qx] * wq1[qy] * wq1[qz] * J;
+    double* out = partial + (((size_t)g * gridDim.x + e) * nq3 + q) * 4;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) out[d] = w * acc[qi][d];
+  }
+}
+
+// dV[e][q] += alpha sum_g partial[g][e][q][0], dB[e][q][d] += alpha sum_g partial[g][e][q][1 + d]
+__global__ void cross_density_reduce_kernel(const double* __restrict__ partial, int64_t n_points, int n_groups,
+                                            double alpha, double* __restrict__ dV, double* __restrict__ dB) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_points;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < n_groups; ++g)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) s[d] += partial[((size_t)g * n_points + p) * 4 + d];
+    dV[p] += alpha * s[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dB[p * 3 + d] += alpha * s[1 + d];
   }
 }
 
@@ -675,15 +692,26 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
   const int CC = (int)std::max<size_t>(1, std::min<size_t>(4, budget / per_cc));
   const size_t sh = CC * per_cc + np1 * nq * sizeof(double);
   CHFSI_CHECK(sh <= 160 * 1024, CHFSI_EINVAL, "adjoint: cell too large for LDS");
-  DevBuf<double> b1, wq;
-  b1.upload(c->ref.B.data(), c->ref.B.size(), c->stream);
-  wq.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
+  if (c->ref_b1.n == 0) {
+    c->ref_b1.upload(c->ref.B.data(), c->ref.B.size(), c->stream);
+    c->ref_wq.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
+  }
+  // column groups: enough (cell, group) blocks to fill the GPU, whole CC chunks each
+  const int max_groups = std::max(1, cdiv(n_vec, CC));
+  const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
+  int groups = std::min(max_groups, want);
+  const int cpg = CC * cdiv(cdiv(n_vec, groups), CC);
+  groups = cdiv(n_vec, cpg);
+  const int64_t n_points = (int64_t)c->n_cells * c->nq3;
+  c->cd_partial.alloc((size_t)groups * n_points * 4);
   StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, 2.0 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
-  hipLaunchKernelGGL(cross_density_kernel, dim3(c->n_cells), dim3(256), sh, c->stream, L, ldl, Y, ldy, n_vec,
-                     c->cell_nodes.ptr, c->minv_sqrt.ptr, b1.ptr, wq.ptr, c->J, np1, nq, c->nloc, maxsz, CC,
-                     alpha, dV, dB);
+  hipLaunchKernelGGL(cross_density_kernel, dim3(c->n_cells, groups), dim3(256), sh, c->stream, L, ldl, Y, ldy,
+                     n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->ref_b1.ptr, c->ref_wq.ptr, c->J, np1, nq,
+                     c->nloc, maxsz, CC, cpg, c->cd_partial.ptr);
   LAUNCH_CHECK();
-  CHFSI_HIP(hipStreamSynchronize(c->stream));   // b1, wq leave scope
+  hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
+                     dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, alpha, dV, dB);
+  LAUNCH_CHECK();
 }
 
 // ============================================================================
