@@ -242,7 +242,9 @@ typedef struct {
   int n_vec;
 } chfsi_batch_task;
 enum chfsi_batch_flags {
-  CHFSI_BATCH_AUTOTUNE = 1,  /* time column tile widths 32/64/128 per task at create, keep the fastest */
+  CHFSI_BATCH_AUTOTUNE = 1,  /* time column tile widths 128/64/32 per task at create and keep the
+                                fastest (a narrower width must win by more than 1 %); without it the
+                                widest width <= n_vec is used */
   CHFSI_BATCH_GRAPH = 2      /* capture the whole filter into a hipGraph and replay it while the bounds
                                 are unchanged (needs a non-default stream) */
 };
