@@ -723,7 +723,7 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
 // stages of 8, k-major ([k][m] and [k][n]) so that every fragment read is 16
 // consecutive complex values.  The next stage's global loads are issued before
 // the current stage's MFMAs.
-constexpr int kGM = 128, kGN = 64, kGK = 8, kGPad = 4;
+constexpr int kGM = 128, kGN = 64, kGK = 8, kGPad = 2;   // pad: k rows 4 apart on other banks
 
 struct GemmSmem {
   double2 a[2][kGK][kGM + kGPad];
@@ -775,9 +775,11 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X
   const int i0 = tl.x * kGM, j0 = tl.y * kGN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave & 1, wn = wave >> 1;
-  // staging map: A 8 rows x 128 cols (4 per thread), B 8 rows x 64 cols (2 per thread)
-  const int ak = tid >> 5, am = (tid & 31) * 4;
-  const int bk = tid >> 5, bn = (tid & 31) * 2;
+  // staging map: A 8 rows x 128 cols (4 per thread), B 8 rows x 64 cols (2 per thread);
+  // slot u of a thread is column (tid & 31) + 32 u, so each LDS store writes 32
+  // consecutive elements of a row (no bank conflicts) and each load reads 512 B
+  const int ak = tid >> 5, am = tid & 31;
+  const int bk = tid >> 5, bn = tid & 31;
   d4 cr[4][2], ci[4][2];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -791,7 +793,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X
     const double2* xp = X + (rv ? r : 0) * ldx;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int c = i0 + am + u;
+      const int c = i0 + am + 32 * u;
       pa[u] = (rv && c < n) ? xp[c] : double2{0.0, 0.0};
     }
     const int64_t rb = r0 + bk;
@@ -799,15 +801,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ X
     const double2* yp = Y + (rbv ? rb : 0) * ldy;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int c = j0 + bn + u;
+      const int c = j0 + bn + 32 * u;
       pb[u] = (rbv && c < n) ? yp[c] : double2{0.0, 0.0};
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sm.a[buf][ak][am + u] = pa[u];
+    for (int u = 0; u < 4; ++u) sm.a[buf][ak][am + 32 * u] = pa[u];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + u] = pb[u];
+    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + 32 * u] = pb[u];
   };
   for (int64_t ch = g; ch < n_chunks; ch += n_groups) {
     const int64_t r_begin = ch * chunk_rows;
@@ -916,9 +918,9 @@ __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave & 1, wn = wave >> 1;
   // staging map: A 128 panel rows x 8 k (4 consecutive k per thread, stored
-  // k-major), B 8 rows of Q x 64 columns (2 per thread)
+  // k-major), B 8 rows of Q x 64 columns (columns (tid & 31) + 32 u)
   const int am = tid >> 1, ak = (tid & 1) * 4;
-  const int bk = tid >> 5, bn = (tid & 31) * 2;
+  const int bk = tid >> 5, bn = tid & 31;
   d4 cr[4][2], ci[4][2];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -937,7 +939,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__
     const int kb = k0 + bk;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int cj = j0 + bn + u;
+      const int cj = j0 + bn + 32 * u;
       pb[u] = (kb < kend && cj < n) ? Q[(size_t)kb * n + cj] : double2{0.0, 0.0};
     }
   };
@@ -945,7 +947,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__
 #pragma unroll
     for (int u = 0; u < 4; ++u) sm.a[buf][ak + u][am] = pa[u];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + u] = pb[u];
+    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + 32 * u] = pb[u];
   };
   const int nst = (kend + kGK - 1) / kGK;
   gload(0);
