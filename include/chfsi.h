@@ -224,6 +224,35 @@ int chfsi_cheb_filter_backward(chfsi_ctx* ctx, int ik, const void* X_d, int64_t 
                                double b, double a0, int ckpt_every, void* work_d, size_t work_bytes,
                                double* dV_d, double* dB_d);
 
+/* ---- Densities from the Rayleigh-Ritz output (eqn:rho, eqn:mag), with
+ * Fermi-Dirac occupations at the smearing temperature of Sec. V and the entropy
+ * term of the free energy in Sec. II.C. */
+
+/* Fermi-Dirac occupations of n levels (host, float64): occ_h[i] =
+ * 1 / (1 + exp((eps_h[i] - mu) / kT)) with mu chosen by bisection so that
+ * sum_i w_h[i] occ_h[i] = n_electrons (w_h NULL: all weights 1; a weight is the
+ * k-point weight of the level's k-point).  Writes mu to *mu_h and
+ * E_ent = kT sum_i w_i [f_i ln f_i + (1 - f_i) ln(1 - f_i)] to *e_ent_h (each may
+ * be NULL).  kT in Ha (500 K = 1.5834e-3 Ha).  CHFSI_EINVAL unless kT > 0,
+ * every w_i >= 0, every eps finite and 0 < n_electrons < sum_i w_i.  Needs no
+ * context and no GPU; its errors are read with chfsi_last_error(NULL). */
+int chfsi_fermi_dirac(int n, const double* eps_h, const double* w_h, double n_electrons, double kT,
+                      double* occ_h, double* mu_h, double* e_ent_h);
+
+/* ADDS the occupation-weighted density and magnetisation of one block into
+ * rho_d [E][nq^3] and mag_d [E][nq^3][3] (device, float64, cell-major as the
+ * fields of chfsi_set_local; the caller zeroes them before the first block):
+ *   rho(e,q)   += sum_n occ_h[n] u_n(q)^H u_n(q),
+ *   mag_d(e,q) += sum_n occ_h[n] u_n(q)^H sigma_d u_n(q),
+ * where u_n(q) = sum_i N_i(r_q) (M_D^{-1/2} x_n)_i is the spinor field of column n
+ * of X_d [2M][ldx] at the quadrature point.  With psi = exp(ik.r) u the densities
+ * depend on u only, so a k-point grid calls this once per k-point with
+ * occ_h[n] = w_k f_nk (host, n_vec values, read before the call returns).  FP64;
+ * needs the mesh only (not chfsi_set_local).  Requires n_q <= 10.  The sums over
+ * n run in a fixed order: repeated calls give identical results. */
+int chfsi_density(chfsi_ctx* ctx, const void* X_d, int64_t ldx, int n_vec, const double* occ_h,
+                  double* rho_d, double* mag_d);
+
 /* ---- Batched filtering of independent operators (the k-points of a grid and
  * independent systems: the eigenproblems of different k are independent,
  * Sec. III.B).  One task = one (context, k-point, block): X_d [2M][ldx] is

@@ -67,3 +67,22 @@ def density_magnetisation(mesh, M_D, X, occ):
     for d in range(3):
         m[:, :, d] = np.real(np.einsum("eqan,ab,eqbn,n->eq", xq.conj(), PAULI[d], xq, f))
     return rho, m
+
+
+def density_at_cells(mesh, M_D, rows_fn, cells, occ):
+    """density_magnetisation restricted to the listed cells, the block's rows read
+    through rows_fn(row_indices) -> [len(rows), n] so that a large block need not
+    exist on the host.  Returns rho [len(cells), nq^3], m [len(cells), nq^3, 3]."""
+    f = np.asarray(occ, dtype=np.float64)
+    nq3 = mesh.nq ** 3
+    rho = np.zeros((len(cells), nq3))
+    m = np.zeros((len(cells), nq3, 3))
+    for i, e in enumerate(cells):
+        g = mesh.cell_nodes(e)
+        rows = np.stack([2 * g, 2 * g + 1], axis=1).ravel()
+        Z = np.asarray(rows_fn(rows)).reshape(len(g), 2, -1) / np.sqrt(M_D[g])[:, None, None]
+        u = np.einsum("iq,ian->qan", mesh.Nt, Z)                 # [q, alpha, n]
+        rho[i] = np.real(np.einsum("qan,qan,n->q", u.conj(), u, f))
+        for d in range(3):
+            m[i, :, d] = np.real(np.einsum("qan,ab,qbn,n->q", u.conj(), PAULI[d], u, f))
+    return rho, m

@@ -16,7 +16,8 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_last_error", "chfsi_version", "chfsi_stats_enable", "chfsi_stats_read",
             "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
             "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
-            "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid"]
+            "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid",
+            "chfsi_fermi_dirac", "chfsi_density"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -92,6 +93,8 @@ def load():
         "chfsi_filter_backward_workspace": ([vp, i32, i32, i32], C.c_size_t),
         "chfsi_cheb_filter_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, i32, dbl, dbl, dbl,
                                         i32, vp, C.c_size_t, vp, vp], i32),
+        "chfsi_fermi_dirac": ([i32, pd, pd, dbl, dbl, pd, pd, pd], i32),
+        "chfsi_density": ([vp, vp, i64, i32, pd, vp, vp], i32),
         "chfsi_stats_enable": ([vp, i32], i32),
         "chfsi_stats_read": ([vp, C.POINTER(StageStats)], i32),
         "chfsi_stats_reset": ([vp], i32),

@@ -238,6 +238,20 @@ class Operator:
             work.numel() * work.element_size(), C.c_void_p(dV.data_ptr()), C.c_void_p(dB.data_ptr())))
         return Xbar
 
+    # ---------------------------------------------------------------- densities
+    def density(self, X, occ, rho, mag):
+        """rho += sum_n occ[n] u_n^H u_n, mag += sum_n occ[n] u_n^H sigma u_n at every
+        quadrature point; rho [E, nq^3], mag [E, nq^3, 3] float64 CUDA tensors."""
+        px, ldx, n = _block(X, "X")
+        f = np.ascontiguousarray(np.asarray(occ, dtype=np.float64).reshape(-1))
+        if f.shape[0] != n:
+            raise ValueError("occ must hold one value per column of X")
+        self._fields_grad(rho, mag)
+        self._chk(self.lib.chfsi_density(self.ctx, C.c_void_p(px), ldx, n,
+                                         f.ctypes.data_as(C.POINTER(C.c_double)),
+                                         C.c_void_p(rho.data_ptr()), C.c_void_p(mag.data_ptr())))
+        return rho, mag
+
     def stats_enable(self, on: bool = True):
         self._chk(self.lib.chfsi_stats_enable(self.ctx, 1 if on else 0))
 
@@ -257,6 +271,25 @@ class Operator:
 
 BATCH_AUTOTUNE = 1
 BATCH_GRAPH = 2
+
+
+def fermi_dirac(eps, n_electrons: float, kT: float, weights=None):
+    """(occupations, mu, E_ent) of the levels eps at temperature kT (Ha) holding
+    n_electrons; weights are the levels' k-point weights (default 1)."""
+    lib = _lib.load()
+    e = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).reshape(-1))
+    pd = C.POINTER(C.c_double)
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if w.shape != e.shape:
+            raise ValueError("weights must match eps")
+    occ = np.empty_like(e)
+    mu, ent = C.c_double(0.0), C.c_double(0.0)
+    rc = lib.chfsi_fermi_dirac(e.shape[0], e.ctypes.data_as(pd), None if w is None else w.ctypes.data_as(pd),
+                               float(n_electrons), float(kT), occ.ctypes.data_as(pd), C.byref(mu), C.byref(ent))
+    _lib.check(rc)
+    return occ, mu.value, ent.value
 
 
 class Batch:

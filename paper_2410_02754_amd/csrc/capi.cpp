@@ -433,6 +433,83 @@ int chfsi_lanczos_bounds(chfsi_ctx* c, int ik, int steps, const void* v0, double
   API_END(c)
 }
 
+// Fermi-Dirac occupation of one level: 1 / (1 + exp((eps - mu) / kT)) in a form
+// that neither overflows nor loses the small tail.
+static double fermi_occ(double eps, double mu, double kT) {
+  const double x = (eps - mu) / kT;
+  if (x > 0.0) {
+    const double t = std::exp(-x);
+    return t / (1.0 + t);
+  }
+  return 1.0 / (1.0 + std::exp(x));
+}
+
+static double fermi_count(int n, const double* eps, const double* w, double mu, double kT) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += (w ? w[i] : 1.0) * fermi_occ(eps[i], mu, kT);
+  return s;
+}
+
+int chfsi_fermi_dirac(int n, const double* eps, const double* w, double n_electrons, double kT, double* occ,
+                      double* mu_out, double* e_ent_out) {
+  try {
+    CHFSI_CHECK(n >= 1 && eps && occ, CHFSI_EINVAL, "fermi_dirac: need n >= 1 and non-NULL eps, occ");
+    CHFSI_CHECK(std::isfinite(kT) && kT > 0.0, CHFSI_EINVAL, "fermi_dirac: kT must be positive");
+    double wsum = 0.0, lo = eps[0], hi = eps[0];
+    for (int i = 0; i < n; ++i) {
+      CHFSI_CHECK(std::isfinite(eps[i]), CHFSI_EINVAL, "fermi_dirac: non-finite eigenvalue");
+      const double wi = w ? w[i] : 1.0;
+      CHFSI_CHECK(std::isfinite(wi) && wi >= 0.0, CHFSI_EINVAL, "fermi_dirac: weights must be >= 0");
+      wsum += wi;
+      lo = std::min(lo, eps[i]);
+      hi = std::max(hi, eps[i]);
+    }
+    CHFSI_CHECK(n_electrons > 0.0 && n_electrons < wsum, CHFSI_EINVAL,
+                "fermi_dirac: need 0 < n_electrons < sum of weights");
+    // bracket: the count rises monotonically in mu from 0 to sum w
+    lo -= 50.0 * kT;
+    hi += 50.0 * kT;
+    for (int it = 0; it < 64 && fermi_count(n, eps, w, lo, kT) >= n_electrons; ++it) lo -= (hi - lo);
+    for (int it = 0; it < 64 && fermi_count(n, eps, w, hi, kT) <= n_electrons; ++it) hi += (hi - lo);
+    double mu = 0.5 * (lo + hi);
+    for (int it = 0; it < 400; ++it) {
+      mu = 0.5 * (lo + hi);
+      if (fermi_count(n, eps, w, mu, kT) < n_electrons)
+        lo = mu;
+      else
+        hi = mu;
+      if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(mu))) break;
+    }
+    mu = 0.5 * (lo + hi);
+    double ent = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double f = fermi_occ(eps[i], mu, kT);
+      occ[i] = f;
+      if (f > 0.0 && f < 1.0) ent += (w ? w[i] : 1.0) * (f * std::log(f) + (1.0 - f) * std::log1p(-f));
+    }
+    if (mu_out) *mu_out = mu;
+    if (e_ent_out) *e_ent_out = kT * ent;
+  } catch (const chfsi::Error& e) {
+    g_create_error = e.msg;
+    return e.code;
+  }
+  return CHFSI_OK;
+}
+
+int chfsi_density(chfsi_ctx* c, const void* X, int64_t ldx, int n_vec, const double* occ, double* rho,
+                  double* mag) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  check_block(c, X, ldx, n_vec, "X");
+  CHFSI_CHECK(occ != nullptr, CHFSI_EINVAL, "occ_h is NULL");
+  CHFSI_CHECK(rho && mag, CHFSI_EINVAL, "rho_d and mag_d must be non-NULL");
+  for (int n = 0; n < n_vec; ++n)
+    CHFSI_CHECK(std::isfinite(occ[n]), CHFSI_EINVAL, "occ_h holds a non-finite value");
+  c->occ.upload(occ, (size_t)n_vec, c->stream);
+  densities(c, (const double2*)X, ldx, n_vec, c->occ.ptr, rho, mag);
+  API_END(c)
+}
+
 int chfsi_apply_H_backward(chfsi_ctx* c, int ik, const void* X, int64_t ldx, const void* Ybar, int64_t ldyb,
                            void* Xbar, int64_t ldxb, int n_vec, double* dV, double* dB) {
   if (!c) return CHFSI_EINVAL;

@@ -192,6 +192,7 @@ struct chfsi_ctx {
   chfsi::DevBuf<double> panel;                // row panel for in-place rotations
   chfsi::DevBuf<double> cd_partial;           // adjoint cross densities per column group
   chfsi::DevBuf<double> ref_b1, ref_wq;       // 1-D interpolation table and weights (device copy)
+  chfsi::DevBuf<double> occ;                  // occupations of the last density call (device copy)
   // stage timing
   bool stats_on = false;
   std::vector<chfsi::StageRec> pending;
@@ -249,6 +250,9 @@ void launch_cols_axpby(chfsi_ctx* c, double2* Y, int64_t ldy, const double2* X, 
 // dV[e][q] += alpha w_q J Re sum_n l^H y, dB_d[e][q] += alpha w_q J Re sum_n l^H sigma_d y
 void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
                    double alpha, double* dV, double* dB);
+// rho += sum_n occ_d[n] u_n^H u_n, mag += sum_n occ_d[n] u_n^H sigma u_n at every quadrature point
+void densities(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* occ_d, double* rho,
+               double* mag);
 void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,
                        int64_t rows, int n_vec, double beta, double gamma);
 void launch_copy_rows(chfsi_ctx* c, double2* dst, int64_t ldd, const double2* src, int64_t lds,

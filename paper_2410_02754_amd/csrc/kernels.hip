@@ -555,15 +555,21 @@ void nonlocal_prepare(chfsi_ctx* c, KPoint& kp, int n_vec) {
 // written (times w_q J) to partial[group][cell][point][4]; a second kernel adds
 // the groups in a fixed order into dV, dB.
 constexpr int kCdMaxQ = 4;   // points per thread: nq^3 <= 1024
+// NS = 4 streams (L up, L down, Y up, Y down), or NS = 2 when L = Y (densities:
+// the block is gathered and interpolated once).  colw: per-column weights (the
+// occupations) or null; wJ: multiply by w_q J (the adjoint pairing) or not (the
+// densities themselves).
+template <int NS>
 __global__ __launch_bounds__(256) void cross_density_kernel(
     const double2* __restrict__ L, int64_t ldl, const double2* __restrict__ Y, int64_t ldy, int n_vec,
     const int32_t* __restrict__ cell_nodes, const double* __restrict__ minv_sqrt,
     const double* __restrict__ B1, const double* __restrict__ wq1, double J, int np1, int nq, int nloc,
-    int maxsz, int CC, int cols_per_group, double* __restrict__ partial) {
+    int maxsz, int CC, int cols_per_group, const double* __restrict__ colw, int wJ,
+    double* __restrict__ partial) {
   extern __shared__ double2 sm[];
-  double2* bufA = sm;                               // [CC*4][maxsz]
-  double2* bufB = sm + (size_t)CC * 4 * maxsz;      // [CC*4][maxsz]
-  double* sBt = reinterpret_cast<double*>(bufB + (size_t)CC * 4 * maxsz);   // [np1][nq]
+  double2* bufA = sm;                               // [CC*NS][maxsz]
+  double2* bufB = sm + (size_t)CC * NS * maxsz;     // [CC*NS][maxsz]
+  double* sBt = reinterpret_cast<double*>(bufB + (size_t)CC * NS * maxsz);   // [np1][nq]
   const int e = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
   const int nq3 = nq * nq * nq;
   const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
@@ -574,8 +580,8 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
   const int32_t* nodes = cell_nodes + (size_t)e * nloc;
   for (int n0 = c_begin; n0 < c_end; n0 += CC) {
     // gather: stream s = 2 * operand + spin
-    for (int t = tid; t < CC * 4 * nloc; t += 256) {
-      const int i = t % nloc, s = (t / nloc) % 4, cc = t / (4 * nloc);
+    for (int t = tid; t < CC * NS * nloc; t += 256) {
+      const int i = t % nloc, s = (t / nloc) % NS, cc = t / (NS * nloc);
       const int col = n0 + cc;
       double2 v = {0.0, 0.0};
       if (col < c_end) {
@@ -586,11 +592,11 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
         v.x = sc * z.x;
         v.y = sc * z.y;
       }
-      bufA[(size_t)(cc * 4 + s) * maxsz + i] = v;
+      bufA[(size_t)(cc * NS + s) * maxsz + i] = v;
     }
     __syncthreads();
     // x: T1[qx + nq (ay + np az)] = sum_ax l_ax(qx) Z[ax + np (ay + np az)]
-    for (int t = tid; t < CC * 4 * nq * np1 * np1; t += 256) {
+    for (int t = tid; t < CC * NS * nq * np1 * np1; t += 256) {
       const int o = t % (nq * np1 * np1), st = t / (nq * np1 * np1);
       const int qx = o % nq, rest = o / nq;
       const double2* in = bufA + (size_t)st * maxsz + rest * np1;
@@ -604,7 +610,7 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
     }
     __syncthreads();
     // y: T2[qx + nq (qy + nq az)] = sum_ay l_ay(qy) T1[qx + nq (ay + np az)]
-    for (int t = tid; t < CC * 4 * nq * nq * np1; t += 256) {
+    for (int t = tid; t < CC * NS * nq * nq * np1; t += 256) {
       const int o = t % (nq * nq * np1), st = t / (nq * nq * np1);
       const int qx = o % nq, qy = (o / nq) % nq, az = o / (nq * nq);
       const double2* in = bufB + (size_t)st * maxsz;
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
     }
     __syncthreads();
     // z: Zq[qx + nq (qy + nq qz)] = sum_az l_az(qz) T2[qx + nq (qy + nq az)]
-    for (int t = tid; t < CC * 4 * nq3; t += 256) {
+    for (int t = tid; t < CC * NS * nq3; t += 256) {
       const int o = t % nq3, st = t / nq3;
       const int qxy = o % (nq * nq), qz = o / (nq * nq);
       const double2* in = bufA + (size_t)st * maxsz;
@@ -638,8 +644,11 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
       const int q = tid + 256 * qi;
       if (q >= nq3) continue;
       for (int cc = 0; cc < CC; ++cc) {
-        const double2 l0 = bufB[(size_t)(cc * 4 + 0) * maxsz + q], l1 = bufB[(size_t)(cc * 4 + 1) * maxsz + q];
-        const double2 y0 = bufB[(size_t)(cc * 4 + 2) * maxsz + q], y1 = bufB[(size_t)(cc * 4 + 3) * maxsz + q];
+        if (n0 + cc >= c_end) break;
+        const double cw = colw ? colw[n0 + cc] : 1.0;
+        const double2 l0 = bufB[(size_t)(cc * NS + 0) * maxsz + q], l1 = bufB[(size_t)(cc * NS + 1) * maxsz + q];
+        const double2 y0 = bufB[(size_t)(cc * NS + NS - 2) * maxsz + q];
+        const double2 y1 = bufB[(size_t)(cc * NS + NS - 1) * maxsz + q];
         // conj(l_a) y_b = (lr - i li)(yr + i yi)
         const double r00 = l0.x * y0.x + l0.y * y0.y, i00 = l0.x * y0.y - l0.y * y0.x;
         const double r11 = l1.x * y1.x + l1.y * y1.y, i11 = l1.x * y1.y - l1.y * y1.x;
@@ -647,10 +656,10 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
         const double r10 = l1.x * y0.x + l1.y * y0.y, i10 = l1.x * y0.y - l1.y * y0.x;
         (void)i00;
         (void)i11;
-        acc[qi][0] += r00 + r11;          // 1
-        acc[qi][1] += r01 + r10;          // sigma_x
-        acc[qi][2] += i01 - i10;          // sigma_y: Re(conj(l0)(-i y1) + conj(l1)(i y0))
-        acc[qi][3] += r00 - r11;          // sigma_z
+        acc[qi][0] += cw * (r00 + r11);   // 1
+        acc[qi][1] += cw * (r01 + r10);   // sigma_x
+        acc[qi][2] += cw * (i01 - i10);   // sigma_y: Re(conj(l0)(-i y1) + conj(l1)(i y0))
+        acc[qi][3] += cw * (r00 - r11);   // sigma_z
       }
     }
     __syncthreads();
@@ -660,7 +669,7 @@ __global__ __launch_bounds__(256) void cross_density_kernel(
     const int q = tid + 256 * qi;
     if (q >= nq3) continue;
     const int qx = q % nq, qy = (q / nq) % nq, qz = q / (nq * nq);
-    const double w = wq1[qx] * wq1[qy] * wq1[qz] * J;
+    const double w = wJ ? wq1[qx] * wq1[qy] * wq1[qz] * J : 1.0;
     double* out = partial + (((size_t)g * gridDim.x + e) * nq3 + q) * 4;
 #pragma unroll
     for (int d = 0; d < 4; ++d) out[d] = w * acc[qi][d];
@@ -682,16 +691,19 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
   }
 }
 
-void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
-                   double alpha, double* dV, double* dB) {
+// Shared launcher: partial sums per (cell, column group), then the fixed-order
+// group reduction adding alpha * (sums) into (dV, dB).
+template <int NS>
+static void launch_cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy,
+                                 int n_vec, const double* colw, int wJ, double alpha, double* dV, double* dB) {
   const int np1 = c->np1, nq = c->nq;
   const int maxsz = std::max(std::max(c->nloc, nq * np1 * np1), std::max(nq * nq * np1, c->nq3));
-  CHFSI_CHECK(c->nq3 <= 256 * kCdMaxQ, CHFSI_EINVAL, "adjoint supports n_q <= 10");
-  const size_t per_cc = 2 * 4 * (size_t)maxsz * sizeof(double2);
+  CHFSI_CHECK(c->nq3 <= 256 * kCdMaxQ, CHFSI_EINVAL, "quadrature-point fields support n_q <= 10");
+  const size_t per_cc = 2 * NS * (size_t)maxsz * sizeof(double2);
   const size_t budget = 128 * 1024;
   const int CC = (int)std::max<size_t>(1, std::min<size_t>(4, budget / per_cc));
   const size_t sh = CC * per_cc + np1 * nq * sizeof(double);
-  CHFSI_CHECK(sh <= 160 * 1024, CHFSI_EINVAL, "adjoint: cell too large for LDS");
+  CHFSI_CHECK(sh <= 160 * 1024, CHFSI_EINVAL, "quadrature-point fields: cell too large for LDS");
   if (c->ref_b1.n == 0) {
     c->ref_b1.upload(c->ref.B.data(), c->ref.B.size(), c->stream);
     c->ref_wq.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
@@ -704,14 +716,24 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
   groups = cdiv(n_vec, cpg);
   const int64_t n_points = (int64_t)c->n_cells * c->nq3;
   c->cd_partial.alloc((size_t)groups * n_points * 4);
-  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, 2.0 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
-  hipLaunchKernelGGL(cross_density_kernel, dim3(c->n_cells, groups), dim3(256), sh, c->stream, L, ldl, Y, ldy,
-                     n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->ref_b1.ptr, c->ref_wq.ptr, c->J, np1, nq,
-                     c->nloc, maxsz, CC, cpg, c->cd_partial.ptr);
+  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, (double)NS / 2 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
+  hipLaunchKernelGGL(cross_density_kernel<NS>, dim3(c->n_cells, groups), dim3(256), sh, c->stream, L, ldl, Y,
+                     ldy, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->ref_b1.ptr, c->ref_wq.ptr, c->J, np1, nq,
+                     c->nloc, maxsz, CC, cpg, colw, wJ, c->cd_partial.ptr);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
                      dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, alpha, dV, dB);
   LAUNCH_CHECK();
+}
+
+void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
+                   double alpha, double* dV, double* dB) {
+  launch_cross_density<4>(c, L, ldl, Y, ldy, n_vec, nullptr, 1, alpha, dV, dB);
+}
+
+void densities(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* occ_d, double* rho,
+               double* mag) {
+  launch_cross_density<2>(c, X, ldx, X, ldx, n_vec, occ_d, 0, 1.0, rho, mag);
 }
 
 // ============================================================================

@@ -1,0 +1,55 @@
+"""chfsi_fermi_dirac (host logic of the library, no GPU) against the oracle's
+Fermi-Dirac occupations (Sec. V smearing, Sec. II.C entropy), and its argument
+checks."""
+import numpy as np
+import pytest
+
+from oracle import density as od
+
+
+@pytest.mark.parametrize("seed,n,frac,temp", [(0, 1, 0.5, 500.0), (1, 7, 0.3, 500.0), (2, 96, 0.61, 500.0),
+                                              (3, 512, 0.87, 500.0), (4, 40, 0.5, 5.0), (5, 40, 0.5, 1e5)])
+def test_fermi_dirac_matches_oracle(seed, n, frac, temp):
+    from paper_2410_02754_amd import fermi_dirac
+    rng = np.random.default_rng(seed)
+    eps = np.sort(rng.uniform(-0.8, 0.4, size=n))
+    w = rng.uniform(0.05, 1.0, size=n) if seed % 2 else None
+    wsum = n if w is None else w.sum()
+    kT = temp * od.KELVIN_TO_HA
+    f_o, mu_o, ent_o = od.fermi_dirac(eps, frac * wsum, kT, w)
+    f, mu, ent = fermi_dirac(eps, frac * wsum, kT, w)
+    assert np.abs(f - f_o).max() < 1e-12
+    ww = np.ones(n) if w is None else w
+    # mu is unique but, with the Fermi level in a gap much wider than kT, the count
+    # hardly moves with it: compare mu through the count change it would cause
+    dN_dmu = float((ww * f_o * (1.0 - f_o)).sum()) / kT
+    assert abs(mu - mu_o) * dN_dmu < 1e-11 * wsum
+    assert abs(ent - ent_o) < 1e-12 * max(kT, abs(ent_o))
+    assert abs((ww * f).sum() - frac * wsum) < 1e-11 * wsum
+
+
+def test_fermi_dirac_degenerate_levels_share_occupation():
+    from paper_2410_02754_amd import fermi_dirac
+    eps = np.array([-0.2, 0.1, 0.1, 0.1, 0.3])
+    f, mu, _ = fermi_dirac(eps, 2.5, 500 * od.KELVIN_TO_HA)
+    assert f[1] == f[2] == f[3]
+    assert abs(f[1] - 0.5) < 1e-12 and abs(mu - 0.1) < 1e-9
+
+
+@pytest.mark.parametrize("args", [(0, [0.1], None, 0.5, 1e-3), (2, [0.1, 0.2], None, 2.0, 1e-3),
+                                  (2, [0.1, 0.2], None, 0.0, 1e-3), (2, [0.1, 0.2], None, 1.0, 0.0),
+                                  (2, [0.1, np.nan], None, 1.0, 1e-3), (2, [0.1, 0.2], [1.0, -0.5], 0.2, 1e-3)])
+def test_fermi_dirac_rejects_bad_arguments(args):
+    import ctypes as C
+    from paper_2410_02754_amd import _lib
+    lib = _lib.load()
+    n, eps, w, ne, kT = args
+    pd = C.POINTER(C.c_double)
+    e = np.asarray(eps + [0.0], dtype=np.float64)
+    wa = None if w is None else np.asarray(w, dtype=np.float64)
+    occ = np.zeros(3)
+    mu, ent = C.c_double(), C.c_double()
+    rc = lib.chfsi_fermi_dirac(n, e.ctypes.data_as(pd), None if wa is None else wa.ctypes.data_as(pd), ne, kT,
+                               occ.ctypes.data_as(pd), C.byref(mu), C.byref(ent))
+    assert rc == -1
+    assert lib.chfsi_last_error(None)

@@ -84,3 +84,17 @@ def test_density_of_a_uniform_spinor():
     bloch = np.array([np.sin(0.8) * np.cos(0.9), np.sin(0.8) * np.sin(0.9), np.cos(0.8)])
     assert np.allclose(rho, 2.0 * c * c, atol=1e-14)
     assert np.allclose(m, 2.0 * c * c * bloch[None, None, :], atol=1e-14)
+
+
+def test_density_at_cells_agrees_with_the_whole_mesh_form():
+    s = synth.make_system("dens2", n_cells=(2, 3, 2), box=(4.0, 5.0, 4.0), p=3, n_atoms=1, lmax=1,
+                          rcut_sigmas=5.0, n_vec=4)
+    mesh = ham.mesh_for(s)
+    MD = mesh.lumped_mass()
+    X = synth.random_block(2, s.n_dof, 4)
+    f = [1.0, 0.5, 0.25, 0.0]
+    rho, m = od.density_magnetisation(mesh, MD, X, f)
+    cells = [0, 5, 11]
+    rc, mc = od.density_at_cells(mesh, MD, lambda r: X[r], cells, f)
+    assert np.allclose(rc, rho[cells], rtol=0, atol=1e-13 * rho.max())
+    assert np.allclose(mc, m[cells], rtol=0, atol=1e-13 * rho.max())
