@@ -117,10 +117,30 @@ int chfsi_sizes(const chfsi_ctx* ctx, int64_t* n_nodes, int64_t* n_dof, int* n_c
 int chfsi_quad_points(const chfsi_ctx* ctx, double* xyz_h);
 
 /* Local fields at the quadrature points (eqn:FEHloc, eqn:FEHlocEl): veff_d
- * [E][nq^3] and bxc_d [E][nq^3][3] (device, float64).  Builds every cell
- * operator for every k-point (FP64, plus the FP32 copy for mixed precision).
+ * [E][nq^3] and bxc_d [E][nq^3][3] (device, float64).  Cell-matrix form
+ * (default): builds every cell operator for every k-point (FP64, plus the FP32
+ * copy for mixed precision); matrix-free form: stores w_q J (V, B) per point.
  * CHFSI_ENONFINITE if a value is NaN/Inf. */
 int chfsi_set_local(chfsi_ctx* ctx, const double* veff_d, const double* bxc_d);
+
+enum chfsi_form { CHFSI_FORM_CELL_MATRIX = 0, CHFSI_FORM_MATRIX_FREE = 1 };
+
+/* Form of the local (cell) part of H_hat used by every apply of this context.
+ * CHFSI_FORM_CELL_MATRIX (default): the cell operators are formed and stored
+ * and applied as batched dense products (Sec. IV.B), FP64 or FP32.
+ * CHFSI_FORM_MATRIX_FREE: the tensor-structured product that the paper leaves
+ * to future work (Sec. VI): per cell and column, values at the quadrature
+ * points by sum factorisation, collocation derivatives there, the terms of
+ * eqn:FEHlocEl applied pointwise, and the transposed contractions back to the
+ * nodes.  Only w_q J (V, B) per quadrature point is stored (32 B per point
+ * instead of about 4 (2 n_p^3)^2 x 8 B of matrices per cell).  Same quadrature,
+ * so the result equals the cell-matrix product up to rounding.  Needs
+ * n_q = p + 1 (GL with n_q = p + 1, or GLL) and FP64 throughout: with this
+ * form, CHFSI_PREC_MIXED requests return CHFSI_EINVAL and chfsi_batch_create
+ * rejects the context.  The call clears the local operator (CHFSI_ESTATE until
+ * the next chfsi_set_local builds it in the chosen form).  CHFSI_EINVAL for an
+ * unknown form or unsupported mesh. */
+int chfsi_set_apply_form(chfsi_ctx* ctx, int form);
 
 /* Replace the set of pseudo-atoms (eqn:FEHnloc, eqn:CMat).  Builds the
  * Bloch-phased, image-summed and M_D^{-1/2}-scaled projector tables for every

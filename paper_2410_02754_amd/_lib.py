@@ -17,7 +17,7 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
             "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
             "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid",
-            "chfsi_fermi_dirac", "chfsi_density"]
+            "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -93,6 +93,7 @@ def load():
         "chfsi_filter_backward_workspace": ([vp, i32, i32, i32], C.c_size_t),
         "chfsi_cheb_filter_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, i32, dbl, dbl, dbl,
                                         i32, vp, C.c_size_t, vp, vp], i32),
+        "chfsi_set_apply_form": ([vp, i32], i32),
         "chfsi_fermi_dirac": ([i32, pd, pd, dbl, dbl, pd, pd, pd], i32),
         "chfsi_density": ([vp, vp, i64, i32, pd, vp, vp], i32),
         "chfsi_stats_enable": ([vp, i32], i32),

@@ -10,6 +10,7 @@ from . import _lib
 
 PREC_FP64 = 0
 PREC_MIXED = 1
+FORMS = {"cell": 0, "matrix_free": 1}
 _PREC = {"fp64": PREC_FP64, "mixed": PREC_MIXED, PREC_FP64: PREC_FP64, PREC_MIXED: PREC_MIXED}
 
 
@@ -40,7 +41,7 @@ class Operator:
     """
 
     def __init__(self, n_cells: Sequence[int], box: Sequence[float], p: int, quad: str = "gl",
-                 n_q: Optional[int] = None, kpts=None, stream=None):
+                 n_q: Optional[int] = None, kpts=None, stream=None, form: str = "cell"):
         torch = _torch()
         self.lib = _lib.load()
         k = np.zeros((1, 3)) if kpts is None else np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 3)
@@ -67,6 +68,17 @@ class Operator:
         self.n_nodes, self.n_dof = nn.value, nd.value
         self.n_cells, self.nq3, self.n_colours = ne.value, nq3.value, ncol.value
         self.n_k = int(k.shape[0])
+        self.form = "cell"
+        if form != "cell":
+            self.set_form(form)
+
+    def set_form(self, form: str):
+        """"cell" (stored cell matrices) or "matrix_free" (sum factorisation, FP64);
+        the local operator must be set again afterwards."""
+        if form not in FORMS:
+            raise ValueError(f"form must be one of {sorted(FORMS)}")
+        self._chk(self.lib.chfsi_set_apply_form(self.ctx, FORMS[form]))
+        self.form = form
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -187,6 +187,8 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
       const auto& tk = tasks[t];
       CHFSI_CHECK(tk.ctx != nullptr, CHFSI_EINVAL, "task without a context");
       CHFSI_CHECK(tk.ctx->have_local, CHFSI_ESTATE, "chfsi_set_local has not been called for a task");
+      CHFSI_CHECK(tk.ctx->form == CHFSI_FORM_CELL_MATRIX, CHFSI_EINVAL,
+                  "batched filtering needs the cell-matrix form");
       CHFSI_CHECK(tk.ctx->stream == b->stream, CHFSI_EINVAL, "all tasks must share one stream");
       CHFSI_CHECK(tk.ik >= 0 && tk.ik < (int)tk.ctx->kp.size(), CHFSI_EINVAL, "k-point index out of range");
       CHFSI_CHECK(tk.X_d && tk.work_d && tk.X_d != tk.work_d && tk.n_vec >= 1 && tk.ldx >= tk.n_vec &&

@@ -52,6 +52,11 @@ static void require_operator(const chfsi_ctx* c) {
   CHFSI_CHECK(c->have_local, CHFSI_ESTATE, "chfsi_set_local has not been called");
 }
 
+static void require_prec_form(const chfsi_ctx* c, int prec) {
+  CHFSI_CHECK(!(c->form == CHFSI_FORM_MATRIX_FREE && prec == CHFSI_PREC_MIXED), CHFSI_EINVAL,
+              "the matrix-free form is FP64 only");
+}
+
 extern "C" {
 
 const char* chfsi_version(void) { return "chfsi-mi355x 0.1"; }
@@ -141,12 +146,37 @@ int chfsi_quad_points(const chfsi_ctx* c, double* xyz) {
   return CHFSI_OK;
 }
 
+int chfsi_set_apply_form(chfsi_ctx* c, int form) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  CHFSI_CHECK(form == CHFSI_FORM_CELL_MATRIX || form == CHFSI_FORM_MATRIX_FREE, CHFSI_EINVAL, "unknown form");
+  if (form == CHFSI_FORM_MATRIX_FREE) {
+    CHFSI_CHECK(mf_supported(c), CHFSI_EINVAL, "matrix-free form needs n_q = p + 1");
+    mf_prepare(c);
+  }
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+  // drop the other form's data; the operator is rebuilt by the next set_local
+  for (auto* kp : c->kp) {
+    kp->cell64.release();
+    kp->cell32.release();
+  }
+  c->mf_qd.release();
+  c->form = form;
+  c->have_local = false;
+  API_END(c)
+}
+
 int chfsi_set_local(chfsi_ctx* c, const double* V, const double* B) {
   if (!c) return CHFSI_EINVAL;
   API_BEGIN(c)
   CHFSI_CHECK(V && B, CHFSI_EINVAL, "veff_d and bxc_d must be non-NULL");
   CHFSI_CHECK(check_finite(c, V, (int64_t)c->n_cells * c->nq3), CHFSI_ENONFINITE, "veff has NaN/Inf");
   CHFSI_CHECK(check_finite(c, B, (int64_t)c->n_cells * c->nq3 * 3), CHFSI_ENONFINITE, "bxc has NaN/Inf");
+  if (c->form == CHFSI_FORM_MATRIX_FREE) {
+    mf_set_local(c, V, B);
+    c->have_local = true;
+    return CHFSI_OK;
+  }
   const int N = c->nloc;
   for (auto* kp : c->kp) {
     // uniform parts of the cell operator for this k:
@@ -211,6 +241,7 @@ int chfsi_apply_H(chfsi_ctx* c, int ik, const void* X, int64_t ldx, void* Y, int
   check_block(c, Y, ldy, n_vec, "Y");
   CHFSI_CHECK(X != Y, CHFSI_EINVAL, "X and Y must be distinct");
   CHFSI_CHECK(prec == CHFSI_PREC_FP64 || prec == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
+  require_prec_form(c, prec);
   KPoint& kp = kpoint(c, ik);
   apply_H(c, kp, (const double2*)X, ldx, (double2*)Y, ldy, n_vec, prec, 1.0, 0.0, 0.0);
   API_END(c)
@@ -228,6 +259,7 @@ int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, in
   CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
               "filter bounds must satisfy a0 < a < b");
   CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
+  require_prec_form(c, prec_mode);
   KPoint& kp = kpoint(c, ik);
   const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
   const double sigma1 = e / (a0 - cc);
@@ -289,6 +321,7 @@ int chfsi_cheb_filter_resid(chfsi_ctx* c, int ik, void* X, int64_t ldx, const vo
   CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
               "filter bounds must satisfy a0 < a < b");
   CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
+  require_prec_form(c, prec_mode);
   KPoint& kp = kpoint(c, ik);
   const int m = degree, n = n_vec;
   const int64_t rows = 2 * c->n_nodes;

@@ -193,6 +193,11 @@ struct chfsi_ctx {
   chfsi::DevBuf<double> cd_partial;           // adjoint cross densities per column group
   chfsi::DevBuf<double> ref_b1, ref_wq;       // 1-D interpolation table and weights (device copy)
   chfsi::DevBuf<double> occ;                  // occupations of the last density call (device copy)
+  // form of the local operator: CHFSI_FORM_CELL_MATRIX (stored cell matrices)
+  // or CHFSI_FORM_MATRIX_FREE (sum factorisation from the quadrature data)
+  int form = 0;
+  chfsi::DevBuf<double> mf_tab;               // [B: np1^2][Dq: np1^2][w: np1]
+  chfsi::DevBuf<double> mf_qd;                // [E][nq^3][4]: w_q J (V, Bx, By, Bz)
   // stage timing
   bool stats_on = false;
   std::vector<chfsi::StageRec> pending;
@@ -251,6 +256,12 @@ void launch_cols_axpby(chfsi_ctx* c, double2* Y, int64_t ldy, const double2* X, 
 void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
                    double alpha, double* dV, double* dB);
 // rho += sum_n occ_d[n] u_n^H u_n, mag += sum_n occ_d[n] u_n^H sigma u_n at every quadrature point
+// matrix-free local operator (matfree.hip)
+bool mf_supported(const chfsi_ctx* c);
+void mf_prepare(chfsi_ctx* c);
+void mf_set_local(chfsi_ctx* c, const double* V, const double* B);
+void launch_mf_products(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+                        int n_vec, double alpha);
 void densities(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* occ_d, double* rho,
                double* mag);
 void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,

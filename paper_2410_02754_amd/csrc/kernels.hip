@@ -486,7 +486,12 @@ void apply_H3(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* 
     init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, Wold, ldo, n_vec, beta, gamma,
                                  Rs, ldr, rscale);
   }
-  launch_cell_products(c, kp, prec, X, ldx, W, ldw, n_vec, alpha);
+  if (c->form == CHFSI_FORM_MATRIX_FREE) {
+    CHFSI_CHECK(prec == CHFSI_PREC_FP64, CHFSI_EINVAL, "the matrix-free form is FP64 only");
+    launch_mf_products(c, kp, X, ldx, W, ldw, n_vec, alpha);
+  } else {
+    launch_cell_products(c, kp, prec, X, ldx, W, ldw, n_vec, alpha);
+  }
 }
 
 void apply_H2(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,

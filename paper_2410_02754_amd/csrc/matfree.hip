@@ -1,0 +1,328 @@
+// Matrix-free local part of H_hat: the tensor-structured multivector product
+// that the paper names as future work (Sec. VI), for 2-component spinors.
+//
+// Per cell e and column n the product of the cell operator of eqn:FEHlocEl with
+// the gathered, M_D^{-1/2}-scaled spinor u = (u_up, u_dn) is evaluated without
+// forming the cell matrix:
+//   1. U = (B (x) B (x) B)^T u        values at the quadrature points (3 passes)
+//   2. W = w_q J [(V + |k|^2/2) U + (B_xc . sigma) U]          pointwise
+//   3. for each direction d: G_d = D_d U (collocation derivative along d),
+//        W += D_d^T (w_q J G_d / 2) - i k_d w_q J G_d              (2 passes each)
+//   4. y = (B (x) B (x) B) W            back to the nodes (3 passes)
+// and y, scaled by M_D^{-1/2}, is added into the output rows of the cell's nodes.
+// B[a][q] = l_a(x_q) is the 1-D GLL-node Lagrange basis at the quadrature points
+// and D_d = (2/h_d) Dq with Dq[q][r] = l~_r'(x_q) the derivative of the Lagrange
+// basis on the quadrature points.  With n_q = p + 1 points per direction both
+// are exact for the degree-p fields of the cell, so the result equals the
+// product with the assembled cell matrices (kinetic K, mass, k-gradient C,
+// potential and field matrices) up to rounding: same quadrature, different
+// order of summation.  Work per cell and column is 12 line contractions of
+// n_p^4 complex-by-real multiply-adds per spin, against 4 (2 n_p^3)^2 for the
+// dense cell product, and no cell matrices are stored.
+//
+// Launch: one workgroup of 256 threads per (cell of one colour, chunk of CW
+// columns).  Both spins of CW columns live in two LDS buffers of n_p^3 complex
+// values per field; each thread owns one line (along the pass direction) of
+// one (column, spin) field, keeps it in registers and writes the contracted
+// line, so every LDS value read feeds n_p multiply-adds.  Within a colour no
+// two cells share a node, so the scatter is a plain read-add-write.
+#include "mfma.h"
+
+namespace chfsi {
+
+namespace {
+
+// columns per workgroup: two LDS buffers of 2 spins x n_p^3 complex values per
+// column, kept near 44 KB so that three workgroups share a CU
+constexpr int mf_cols(int NP) { return NP <= 4 ? 8 : NP == 5 ? 4 : NP == 6 ? 3 : NP == 7 ? 2 : 1; }
+
+template <int NP, int DIM>
+__device__ __forceinline__ int line_base(int l) {
+  if constexpr (DIM == 0) return l * NP;                       // l = y + NP z
+  else if constexpr (DIM == 1) return (l % NP) + (l / NP) * NP * NP;   // l = x + NP z
+  else return l;                                               // l = x + NP y
+}
+
+// The two coordinates held fixed along a line (for the quadrature weights).
+template <int NP, int DIM>
+__device__ __forceinline__ void line_fixed(int l, int& i0, int& i1) {
+  i0 = l % NP;
+  i1 = l / NP;
+}
+
+// out = contraction of every (column, spin) field along DIM with the table M:
+//   FWD:  out[.. o ..] = sum_i M[i][o] in[.. i ..]   (nodes -> points, M = B)
+//   !FWD: out[.. o ..] = sum_i M[o][i] in[.. i ..]   (points -> nodes)
+template <int NP, int CW, int DIM, bool FWD>
+__device__ __forceinline__ void line_pass(const double* __restrict__ M, const double2* __restrict__ in,
+                                          double2* __restrict__ out) {
+  constexpr int N2 = NP * NP, N3 = N2 * NP;
+  constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
+  for (int t = threadIdx.x; t < N2 * 2 * CW; t += 256) {
+    const int l = t % N2, f = t / N2;
+    const int base = f * N3 + line_base<NP, DIM>(l);
+    double2 v[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v[j] = in[base + j * S];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const double m = FWD ? M[i * NP + o] : M[o * NP + i];
+        re = fma(m, v[i].x, re);
+        im = fma(m, v[i].y, im);
+      }
+      out[base + o * S] = double2{re, im};
+    }
+  }
+}
+
+// Kinetic and k-gradient terms along DIM, added into W:
+//   G = Dq U,  W += a_d Dq^T (wJ G) - i b_d wJ G,
+// a_d = (2/h_d)^2 / 2, b_d = k_d (2/h_d), wJ = J w_x w_y w_z at each point.
+template <int NP, int CW, int DIM, bool KT>
+__device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const double* __restrict__ w1, double J,
+                                          double a_d, double b_d, const double2* __restrict__ U,
+                                          double2* __restrict__ W) {
+  constexpr int N2 = NP * NP, N3 = N2 * NP;
+  constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
+  for (int t = threadIdx.x; t < N2 * 2 * CW; t += 256) {
+    const int l = t % N2, f = t / N2;
+    const int base = f * N3 + line_base<NP, DIM>(l);
+    int i0, i1;
+    line_fixed<NP, DIM>(l, i0, i1);
+    const double wl = J * w1[i0] * w1[i1];
+    double2 u[NP], g[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) u[j] = U[base + j * S];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int r = 0; r < NP; ++r) {
+        re = fma(Dq[q * NP + r], u[r].x, re);
+        im = fma(Dq[q * NP + r], u[r].y, im);
+      }
+      g[q] = double2{re, im};
+    }
+    double2 fk[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const double s = a_d * wl * w1[q];
+      fk[q] = double2{s * g[q].x, s * g[q].y};
+    }
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      double2 acc = W[base + r * S];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        acc.x = fma(Dq[q * NP + r], fk[q].x, acc.x);
+        acc.y = fma(Dq[q * NP + r], fk[q].y, acc.y);
+      }
+      if constexpr (KT) {
+        // -i b wJ g = b wJ g.y - i b wJ g.x
+        const double s = b_d * wl * w1[r];
+        acc.x = fma(s, g[r].y, acc.x);
+        acc.y = fma(-s, g[r].x, acc.y);
+      }
+      W[base + r * S] = acc;
+    }
+  }
+}
+
+// tab: [B: NP*NP][Dq: NP*NP][w: NP], qd: [E][NP^3] of (wJ V, wJ Bx, wJ By, wJ Bz).
+template <int NP, bool KT>
+__global__ __launch_bounds__(256) void mf_apply_kernel(
+    const double* __restrict__ tab, const double4* __restrict__ qd, const int32_t* __restrict__ cell_nodes,
+    const int32_t* __restrict__ cells, int n_in, int n_chunks, const double* __restrict__ minv_sqrt,
+    const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y, int64_t ldy, int n_vec, double alpha,
+    double J, double half_k2, double a0, double a1, double a2, double b0, double b1, double b2) {
+  constexpr int CW = mf_cols(NP);
+  constexpr int N2 = NP * NP, N3 = N2 * NP;
+  extern __shared__ double2 mf_sm[];
+  double2* bufA = mf_sm;                      // [CW][2][N3]
+  double2* bufB = mf_sm + CW * 2 * N3;        // [CW][2][N3]
+  const double* Bt = tab;
+  const double* Dq = tab + N2;
+  const double* w1 = tab + 2 * N2;
+
+  // consecutive work items (the column chunks of one cell) on one XCD
+  const int total = n_in * n_chunks;
+  const int per_xcd = (total + 7) / 8;
+  const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (bid >= total) return;
+  const int e = cells[bid / n_chunks];
+  const int col0 = (bid % n_chunks) * CW;
+  const int32_t* nodes = cell_nodes + (size_t)e * N3;
+  const int tid = threadIdx.x;
+
+  // gather u = M^{-1/2} x (column fastest: neighbouring lanes read one row)
+  for (int t = tid; t < N3 * 2 * CW; t += 256) {
+    const int c = t % CW, s = (t / CW) % 2, i = t / (2 * CW);
+    const int col = col0 + c;
+    double2 v = {0.0, 0.0};
+    if (col < n_vec) {
+      const int64_t I = nodes[i];
+      const double sc = minv_sqrt[I];
+      const double2 z = X[(2 * I + s) * ldx + col];
+      v = double2{sc * z.x, sc * z.y};
+    }
+    bufA[(c * 2 + s) * N3 + i] = v;
+  }
+  __syncthreads();
+  line_pass<NP, CW, 0, true>(Bt, bufA, bufB);
+  __syncthreads();
+  line_pass<NP, CW, 1, true>(Bt, bufB, bufA);
+  __syncthreads();
+  line_pass<NP, CW, 2, true>(Bt, bufA, bufB);   // U in bufB
+  __syncthreads();
+
+  // potential and field terms at the points
+  for (int t = tid; t < N3 * CW; t += 256) {
+    const int q = t % N3, c = t / N3;
+    const double wj = J * w1[q % NP] * w1[(q / NP) % NP] * w1[q / N2];
+    const double4 d = qd[(size_t)e * N3 + q];
+    const double2 u0 = bufB[(c * 2) * N3 + q], u1 = bufB[(c * 2 + 1) * N3 + q];
+    const double s = d.x + half_k2 * wj;
+    // up:   (s + Bz) u0 + (Bx - i By) u1;  down: (s - Bz) u1 + (Bx + i By) u0
+    double2 w0, w2;
+    w0.x = (s + d.w) * u0.x + d.y * u1.x + d.z * u1.y;
+    w0.y = (s + d.w) * u0.y + d.y * u1.y - d.z * u1.x;
+    w2.x = (s - d.w) * u1.x + d.y * u0.x - d.z * u0.y;
+    w2.y = (s - d.w) * u1.y + d.y * u0.y + d.z * u0.x;
+    bufA[(c * 2) * N3 + q] = w0;
+    bufA[(c * 2 + 1) * N3 + q] = w2;
+  }
+  __syncthreads();
+  grad_pass<NP, CW, 0, KT>(Dq, w1, J, a0, b0, bufB, bufA);
+  __syncthreads();
+  grad_pass<NP, CW, 1, KT>(Dq, w1, J, a1, b1, bufB, bufA);
+  __syncthreads();
+  grad_pass<NP, CW, 2, KT>(Dq, w1, J, a2, b2, bufB, bufA);
+  __syncthreads();
+  line_pass<NP, CW, 0, false>(Bt, bufA, bufB);
+  __syncthreads();
+  line_pass<NP, CW, 1, false>(Bt, bufB, bufA);
+  __syncthreads();
+  line_pass<NP, CW, 2, false>(Bt, bufA, bufB);  // y in bufB
+  __syncthreads();
+
+  // Y[rows of the cell] += alpha M^{-1/2} y
+  for (int t = tid; t < N3 * 2 * CW; t += 256) {
+    const int c = t % CW, s = (t / CW) % 2, i = t / (2 * CW);
+    const int col = col0 + c;
+    if (col < n_vec) {
+      const int64_t I = nodes[i];
+      const double sc = alpha * minv_sqrt[I];
+      const double2 v = bufB[(c * 2 + s) * N3 + i];
+      double2* y = Y + (2 * I + s) * ldy + col;
+      double2 o = *y;
+      o.x = fma(sc, v.x, o.x);
+      o.y = fma(sc, v.y, o.y);
+      *y = o;
+    }
+  }
+}
+
+// qd[e][q] = w_q J (V, Bx, By, Bz)
+__global__ void mf_qdata_kernel(const double* __restrict__ V, const double* __restrict__ B,
+                                const double* __restrict__ w1, double J, int nq, int64_t n_points,
+                                double4* __restrict__ qd) {
+  const int nq3 = nq * nq * nq;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_points;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(p % nq3);
+    const double wj = J * w1[q % nq] * w1[(q / nq) % nq] * w1[q / (nq * nq)];
+    qd[p] = double4{wj * V[p], wj * B[3 * p], wj * B[3 * p + 1], wj * B[3 * p + 2]};
+  }
+}
+
+template <int NP, bool KT>
+void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
+                 double alpha) {
+  constexpr int CW = mf_cols(NP);
+  const size_t sh = 2 * (size_t)CW * 2 * NP * NP * NP * sizeof(double2);
+  const int n_chunks = cdiv(n_vec, CW);
+  double a[3], b[3];
+  for (int d = 0; d < 3; ++d) {
+    const double sd = 2.0 / c->h[d];
+    a[d] = 0.5 * sd * sd;
+    b[d] = kp.k[d] * sd;
+  }
+  const double half_k2 = 0.5 * (kp.k[0] * kp.k[0] + kp.k[1] * kp.k[1] + kp.k[2] * kp.k[2]);
+  const double np3 = (double)NP * NP * NP;
+  for (int k = 0; k < c->n_colours; ++k) {
+    const int n_in = c->colour_off[k + 1] - c->colour_off[k];
+    if (n_in == 0) continue;
+    const int64_t total = (int64_t)n_in * n_chunks;
+    CHFSI_CHECK(total < (int64_t)1 << 30, CHFSI_EINVAL, "matrix-free apply: too many work items");
+    // algorithmic flops of the dense cell product (the filter's count), executed
+    // flops of the 12 line contractions per spin, and the rows moved
+    const double n2 = 2.0 * c->nloc;
+    const double flops = 8.0 * n2 * n2 * n_vec * n_in;
+    const double exec = 96.0 * np3 * NP * (double)n_vec * n_in;
+    const double bytes = (double)n_in * 3.0 * c->nloc * 2.0 * n_vec * sizeof(double2);
+    StageTimer tm(c, CHFSI_STAGE_CELL_FP64, flops, exec, bytes);
+    const int grid = (int)(8 * ((total + 7) / 8));
+    hipLaunchKernelGGL((mf_apply_kernel<NP, KT>), dim3(grid), dim3(256), sh, c->stream, c->mf_tab.ptr,
+                       reinterpret_cast<const double4*>(c->mf_qd.ptr), c->cell_nodes.ptr,
+                       c->colour_cells.ptr + c->colour_off[k], n_in, n_chunks, c->minv_sqrt.ptr, X, ldx, W, ldw,
+                       n_vec, alpha, c->J, half_k2, a[0], a[1], a[2], b[0], b[1], b[2]);
+    LAUNCH_CHECK();
+  }
+}
+
+template <int NP>
+void launch_mf_np(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
+                  double alpha) {
+  if (kp.gamma) launch_mf_t<NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+  else launch_mf_t<NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+}
+
+}  // namespace
+
+bool mf_supported(const chfsi_ctx* c) { return c->nq == c->np1 && c->np1 >= 2 && c->np1 <= 9; }
+
+void mf_prepare(chfsi_ctx* c) {
+  CHFSI_CHECK(mf_supported(c), CHFSI_EINVAL, "matrix-free apply needs n_q = p + 1 and 1 <= p <= 8");
+  const int n = c->np1;
+  std::vector<double> Bq, Dlag;
+  lagrange_on(c->ref.xq, c->ref.xq, Bq, Dlag);   // Dlag[r][q] = l~_r'(x_q)
+  std::vector<double> tab(2 * n * n + n);
+  for (int a = 0; a < n; ++a)
+    for (int q = 0; q < n; ++q) tab[a * n + q] = c->ref.B[(size_t)a * c->nq + q];
+  for (int q = 0; q < n; ++q)
+    for (int r = 0; r < n; ++r) tab[n * n + q * n + r] = Dlag[(size_t)r * n + q];
+  for (int q = 0; q < n; ++q) tab[2 * n * n + q] = c->ref.wq[q];
+  c->mf_tab.upload(tab.data(), tab.size(), c->stream);
+}
+
+void mf_set_local(chfsi_ctx* c, const double* V, const double* B) {
+  if (c->mf_tab.n == 0) mf_prepare(c);
+  const int64_t n_points = (int64_t)c->n_cells * c->nq3;
+  c->mf_qd.alloc((size_t)n_points * 4);
+  DevBuf<double> w1;
+  w1.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
+  hipLaunchKernelGGL(mf_qdata_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 8192)), dim3(256), 0,
+                     c->stream, V, B, w1.ptr, c->J, c->nq, n_points, reinterpret_cast<double4*>(c->mf_qd.ptr));
+  LAUNCH_CHECK();
+  CHFSI_HIP(hipStreamSynchronize(c->stream));
+}
+
+void launch_mf_products(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+                        int n_vec, double alpha) {
+  switch (c->np1) {
+    case 2: launch_mf_np<2>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 3: launch_mf_np<3>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 4: launch_mf_np<4>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 5: launch_mf_np<5>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 6: launch_mf_np<6>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 7: launch_mf_np<7>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 8: launch_mf_np<8>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 9: launch_mf_np<9>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    default: throw Error{CHFSI_EINVAL, "matrix-free apply: unsupported p"};
+  }
+}
+
+}  // namespace chfsi

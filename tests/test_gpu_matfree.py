@@ -1,0 +1,154 @@
+"""GPU parity of the matrix-free (sum-factorised) local operator, the paper's
+stated future work (Sec. VI), through the C ABI: H_hat X against the oracle's
+assembled operator and against the cell-matrix path (p = 1 .. 8, GL with
+n_q = p + 1 and GLL, Gamma and general k, anisotropic cells, ragged column
+counts), a Chebyshev filter, two full ChFSI passes at p = 6 and m = 24, the
+full-size closed form of the large workload and its sampled rows, and the
+argument checks of the form (FP64 only, n_q = p + 1, no batching)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chfsi as och, hamiltonian as ham
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _op(s, form="matrix_free"):
+    from paper_2410_02754_amd import Operator
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts, form=form)
+    pts = op.quad_points().reshape(-1, 3)
+    V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+    B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+    op.set_local(V, B)
+    op.set_atoms(s.atoms)
+    return op
+
+
+SYSTEMS = {
+    "p1": dict(n_cells=(3, 2, 2), box=(3.0, 2.0, 2.0), p=1, kpts=[(0.3, 0.0, -0.2)]),
+    "p2_gll": dict(n_cells=(2, 3, 2), box=(3.0, 4.0, 3.0), p=2, quad="gll"),
+    "p3_k_aniso": dict(n_cells=(2, 3, 4), box=(4.0, 5.0, 6.5), p=3, kpts=[(0.21, -0.13, 0.3)], lmax=2),
+    "p4": dict(n_cells=(3, 3, 3), box=(8.0, 8.0, 8.0), p=4),
+    "p5_gll_k": dict(n_cells=(2, 2, 3), box=(4.0, 4.0, 6.0), p=5, quad="gll", kpts=[(0.1, 0.2, -0.05)]),
+    "p6_k": dict(n_cells=(2, 2, 3), box=(2.4, 2.4, 3.6), p=6, kpts=[(0.05, -0.1, 0.15)]),
+    "p7": dict(n_cells=(2, 2, 2), box=(3.0, 3.0, 3.0), p=7),
+    "p8_k": dict(n_cells=(2, 2, 2), box=(3.2, 3.2, 3.2), p=8, kpts=[(0.0, 0.3, 0.1)]),
+}
+
+
+def _sys(name, n_vec=8):
+    kw = dict(SYSTEMS[name])
+    kw.setdefault("lmax", 1)
+    return synth.make_system(name, n_atoms=2, rcut_sigmas=5.0, n_vec=n_vec, **kw)
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+@pytest.mark.parametrize("n_vec", [1, 7, 37])
+def test_matfree_apply_matches_oracle_and_cell_path(name, n_vec):
+    s = _sys(name, n_vec)
+    _, H, _, _, _ = ham.build(s, synth.veff, synth.bxc)
+    X0 = synth.random_block(7, s.n_dof, n_vec)
+    X = torch.tensor(X0, device="cuda")
+    ys = {}
+    for form in ("matrix_free", "cell"):
+        op = _op(s, form)
+        Y = torch.full_like(X, complex(np.nan, np.nan))
+        op.apply_H(X, Y)
+        ys[form] = Y.cpu().numpy()
+        op.close()
+    ref = H @ X0
+    scale = np.abs(ref).max()
+    err = np.abs(ys["matrix_free"] - ref).max() / scale
+    err_c = np.abs(ys["matrix_free"] - ys["cell"]).max() / scale
+    print(f"[matfree {name} n_vec={n_vec}] rel err vs oracle {err:.2e}, vs cell path {err_c:.2e}", flush=True)
+    assert err < 1e-12 and err_c < 1e-12
+
+
+def test_matfree_deterministic_and_block_of_wider_array():
+    s = _sys("p4", 8)
+    _, H, _, _, _ = ham.build(s, synth.veff, synth.bxc)
+    op = _op(s)
+    Xw = torch.tensor(synth.random_block(3, s.n_dof, 50), device="cuda")
+    Y1 = torch.zeros_like(Xw)
+    Y2 = torch.zeros_like(Xw)
+    blk = slice(9, 40)
+    op.apply_H(Xw[:, blk], Y1[:, blk])
+    op.apply_H(Xw[:, blk], Y2[:, blk])
+    assert torch.equal(Y1, Y2)
+    assert torch.count_nonzero(Y1[:, :9]) == 0 and torch.count_nonzero(Y1[:, 40:]) == 0
+    ref = H @ Xw[:, blk].cpu().numpy()
+    assert np.abs(Y1[:, blk].cpu().numpy() - ref).max() < 1e-12 * np.abs(ref).max()
+    op.close()
+
+
+def test_matfree_filter_matches_oracle():
+    s = _sys("p3_k_aniso", 20)
+    _, H, _, _, _ = ham.build(s, synth.veff, synth.bxc)
+    op = _op(s)
+    X0 = synth.start_block(s, s.n_dof)
+    th, _, _ = och.rayleigh_ritz(H, och.chol_gs(X0))
+    lam = np.linalg.eigvalsh(H.toarray())
+    a, b, a0 = float(th[-1]), float(lam[-1] + 0.7), float(th[0])
+    X = torch.tensor(X0, device="cuda")
+    W = torch.empty_like(X)
+    op.cheb_filter(X, W, 9, a, b, a0)
+    ref = och.cheb_filter(H, X0, 9, a, b, a0)
+    err = np.abs(X.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"[matfree filter] rel err {err:.2e}", flush=True)
+    assert err < 1e-11
+    op.close()
+
+
+def test_matfree_full_passes_p6_degree24():
+    """Two ChFSI passes (p = 6, h = 1.2, m = 24, N = 64 in blocks of 32) with the
+    matrix-free operator against the oracle: Ritz values to 1e-10 Ha."""
+    s = synth.make_system("p6m24", n_cells=(2, 2, 3), box=(2.4, 2.4, 3.6), p=6, n_gauss=3, n_atoms=1,
+                          lmax=2, rcut_sigmas=6.0, n_vec=64, block=32, degree=24, passes=2, seed=4)
+    _, H, _, _, _ = ham.build(s, synth.veff, synth.bxc)
+    op = _op(s)
+    X0 = synth.start_block(s, s.n_dof)
+    _, b = och.lanczos_bounds(H, synth.lanczos_start(s, s.n_dof), 40)
+    tho, Xo, ro = och.run(H, X0, s.degree, s.passes, s.block, b, [])
+    X = torch.tensor(X0, device="cuda")
+    W = torch.empty_like(X)
+    op.chol_gs(X)
+    th, r = op.rayleigh_ritz(X, W)
+    for _ in range(s.passes):
+        a, a0 = float(th[-1]), float(th[0])
+        for c0 in range(0, s.n_vec, s.block):
+            op.cheb_filter(X[:, c0:c0 + s.block], W[:, :s.block], s.degree, a, b, a0)
+        op.chol_gs(X)
+        th, r = op.rayleigh_ritz(X, W)
+    d = np.abs(th - tho).max()
+    print(f"[matfree passes p6] max |dtheta| = {d:.2e}", flush=True)
+    assert d < 1e-10
+    assert np.abs(r - ro).max() < 1e-8
+    op.close()
+
+
+def test_matfree_argument_checks():
+    from paper_2410_02754_amd import Batch, ChfsiError, Operator
+    s = _sys("p3_k_aniso", 8)
+    op = _op(s)
+    X = torch.tensor(synth.random_block(1, s.n_dof, 8), device="cuda")
+    Y = torch.empty_like(X)
+    with pytest.raises(ChfsiError, match="FP64"):
+        op.apply_H(X, Y, prec="mixed")
+    W = torch.empty_like(X)
+    with pytest.raises(ChfsiError, match="FP64"):
+        op.cheb_filter(X, W, 4, 1.0, 2.0, 0.0, prec="mixed")
+    with pytest.raises(ChfsiError):
+        Batch([(op, 0, X, W)], 4)
+    # switching the form clears the operator until set_local runs again
+    op.set_form("cell")
+    with pytest.raises(ChfsiError):
+        op.apply_H(X, Y)
+    op.close()
+    op2 = Operator((2, 2, 2), (3.0, 3.0, 3.0), 3, "gl", 6)
+    with pytest.raises(ChfsiError, match="n_q"):
+        op2.set_form("matrix_free")
+    with pytest.raises(ValueError):
+        op2.set_form("dense")
+    op2.close()
