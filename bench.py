@@ -36,6 +36,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6     # TFLOP/s, MI355X dense FP64 (vector = matrix)
 PEAK_FP32 = 157.3    # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0    # GB/s, MI355X HBM3E
+K_B_HA = 3.166811563e-6   # Boltzmann constant, Ha / K
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cell_apply_fp64_scale_traffic.md")
 
 
@@ -71,11 +73,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_operator(s, torch, stream=None):
+def build_operator(s, torch, stream=None, form="cell"):
     import synth
     from paper_2410_02754_amd import Operator
     op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts,
-                  stream=None if stream is None else stream.cuda_stream)
+                  stream=None if stream is None else stream.cuda_stream, form=form)
     t = time.perf_counter()
     pts = op.quad_points().reshape(-1, 3)
     V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
@@ -202,6 +204,7 @@ def main():
                     help="scale (default), batch (k-grid + uneven systems) or adjoint")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-matfree", action="store_true")
     ap.add_argument("--eig-table", default=None,
                     help="write the per-eigenvalue FP64 / mixed table (text) to this path")
     args = ap.parse_args()
@@ -218,6 +221,84 @@ def main():
     else:
         out = bench_scale(args, torch)
     print(json.dumps(out), flush=True)
+
+
+def bench_density(op, s, X, theta, torch, reps=3):
+    """Densities of the FP64 Ritz block (eqn:rho, eqn:mag) with Fermi-Dirac
+    occupations at 500 K (Sec. V), the block holding 15% more states than
+    electrons; HIP-event time of chfsi_density (quadrature-point kernel and the
+    fixed-order group reduction) over the whole block."""
+    from paper_2410_02754_amd import fermi_dirac
+    n_e = float(round(0.85 * s.n_vec))
+    kT = 500.0 * K_B_HA
+    t = time.perf_counter()
+    f, mu, ent = fermi_dirac(theta, n_e, kT)
+    t_fd = time.perf_counter() - t
+    rho = torch.zeros((op.n_cells, op.nq3), dtype=torch.float64, device="cuda")
+    mag = torch.zeros((op.n_cells, op.nq3, 3), dtype=torch.float64, device="cuda")
+    op.density(X, f, rho, mag)                    # first call sizes the partial-sum buffer
+    ts = []
+    for _ in range(reps):
+        rho.zero_()
+        mag.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        op.density(X, f, rho, mag)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sum(ts) / len(ts)
+    n_points = op.n_cells * op.nq3
+    alg_bytes = s.n_dof * s.n_vec * 16 + n_points * 4 * 8          # block read once, rho and m written
+    nq, np1 = s.n_q, s.p + 1
+    # sum factorisation per column, cell and spin: three 1-D passes of complex x real MACs
+    flops = 8.0 * (nq * np1 ** 3 + nq * nq * np1 ** 2 + nq ** 3 * np1) * op.n_cells * s.n_vec
+    mnorm = torch.linalg.norm(mag, dim=-1)
+    res = {"ms": round(ms, 3), "n_electrons": n_e, "kT_Ha": kT, "mu_Ha": mu, "E_ent_Ha": ent,
+           "fermi_dirac_host_ms": round(1e3 * t_fd, 3),
+           "algorithmic_bytes": alg_bytes, "achieved_GBs": round(alg_bytes / (ms * 1e-3) / 1e9, 1),
+           "frac_of_hbm_8000GBs": round(alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM, 4),
+           "interp_flops": flops, "achieved_fp64_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+           "max_rho": float(rho.max()), "max_abs_m_over_rho": float((mnorm / rho.clamp_min(1e-300)).max())}
+    log(f"[bench] densities: {ms:.2f} ms, mu {mu:.6f} Ha, E_ent {ent:.3e} Ha")
+    del rho, mag
+    return res
+
+
+def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch):
+    """The same FP64 passes (same start block, bound and steps) with the
+    matrix-free local operator instead of the stored cell matrices."""
+    t = time.perf_counter()
+    op = build_operator(s, torch, form="matrix_free")
+    t_setup = time.perf_counter() - t
+    op.stats_enable(True)
+    theta, _ = start(op, s, X, W, torch)
+    theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "fp64", torch, "matrix-free warmup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, r, times, ftimes, fst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "fp64", torch, "matrix-free")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    op.close()
+    n_l = max(1, fst["cell_launches"])
+    ms = fst["cell_ms"] / n_l
+    exec_per = fst["cell_exec"] / n_l
+    dth = np.abs(th - theta_ref)
+    res = {"form": "matrix-free sum factorisation, FP64 (n_q = p + 1 collocation)",
+           "s_per_pass": round(total / args.steps, 3),
+           "filter_s_per_pass": round(sum(ftimes) / args.steps, 3),
+           "filter_tflops_cell_count": round(fst["flops"] / sum(ftimes) / 1e12, 4),
+           "setup_s": round(t_setup, 2),
+           "kernel": "mf_apply_kernel<7, false> (gather, 12 line contractions per spin, scatter-add)",
+           "mean_launch_ms": round(ms, 4),
+           "executed_flops_per_launch": exec_per,
+           "executed_fp64_tflops": round(exec_per / (ms * 1e-3) / 1e12, 3) if ms > 0 else None,
+           "executed_frac_of_78.6": round(exec_per / (ms * 1e-3) / 1e12 / PEAK_FP64, 4) if ms > 0 else None,
+           "cell_form_flops_per_launch": fst["cell_flops"] / n_l,
+           "max_dtheta_vs_cell_fp64_Ha": float(dth.max()), "max_resid": float(np.max(r)),
+           "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in fst["stage_ms"].items() if v > 0}}
+    log(f"[bench] matrix-free: {res['s_per_pass']} s per pass, max |dtheta| vs cell {dth.max():.2e} Ha")
+    return res
 
 
 def bench_scale(args, torch):
@@ -287,6 +368,8 @@ def bench_scale(args, torch):
         "theta_min": float(theta64[0]), "theta_max": float(theta64[-1]), "max_resid": float(np.max(r64)),
     }
 
+    out["density"] = bench_density(op, s, X, theta64, torch)
+
     tables = {}
     if not args.no_mixed:
         for key, resid_form in (("mixed", False), ("mixed_resid", True)):
@@ -326,6 +409,8 @@ def bench_scale(args, torch):
             }
             log(f"[bench] {key}: max |dtheta| vs fp64 = {dth.max():.3e} Ha")
     op.close()
+    if not args.no_matfree and s.n_q == s.p + 1:
+        out["matrix_free"] = bench_matfree(args, s, X, W, Wf, b, theta64, torch)
     del X, W, Wf
     if args.eig_table and tables:
         with open(args.eig_table, "w") as fh:

@@ -21,6 +21,7 @@
 
 #include "internal.h"
 #include "mfma.h"
+#include "sumfact.h"
 
 namespace chfsi {
 
@@ -696,11 +697,140 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
   }
 }
 
+// The same sums with n_q = n_p: the gathered fields are interpolated by line
+// passes (one thread per line of a field, sf_line_pass), CW columns of NS
+// streams at a time.  tab = [B: n_p^2][Dq: n_p^2][w: n_p] (matrix-free tables).
+// Work item bid -> cell bid % n_cells, column group bid / n_cells, neighbouring
+// cells (which share face nodes) on one XCD.
+template <int NP, int NS>
+__global__ __launch_bounds__(256) void qfield_sf_kernel(
+    const double2* __restrict__ L, int64_t ldl, const double2* __restrict__ Y, int64_t ldy, int n_vec,
+    const int32_t* __restrict__ cell_nodes, const double* __restrict__ minv_sqrt, const double* __restrict__ tab,
+    double J, int n_cells, int n_groups, int cols_per_group, const double* __restrict__ colw, int wJ,
+    double* __restrict__ partial) {
+  constexpr int CW = NS == 2 ? sf_cols(NP) : (sf_cols(NP) + 1) / 2;
+  constexpr int NF = CW * NS;
+  constexpr int N2 = NP * NP, N3 = N2 * NP;
+  constexpr int QPT = (N3 + 255) / 256;
+  extern __shared__ double2 qf_sm[];
+  double2* bufA = qf_sm;              // [CW][NS][N3]
+  double2* bufB = qf_sm + NF * N3;    // [CW][NS][N3]
+  const double* Bt = tab;
+  const double* w1 = tab + 2 * N2;
+  const int total = n_cells * n_groups;
+  const int per_xcd = (total + 7) / 8;
+  const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (bid >= total) return;
+  const int e = bid % n_cells, g = bid / n_cells, tid = threadIdx.x;
+  const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
+  const int32_t* nodes = cell_nodes + (size_t)e * N3;
+  double acc[QPT][4];
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
+  for (int n0 = c_begin; n0 < c_end; n0 += CW) {
+    // stream s = 2 * operand + spin; column fastest so that lanes share rows
+    for (int t = tid; t < N3 * NS * CW; t += 256) {
+      const int c = t % CW, s = (t / CW) % NS, i = t / (NS * CW);
+      const int col = n0 + c;
+      double2 v = {0.0, 0.0};
+      if (col < c_end) {
+        const int64_t I = nodes[i];
+        const int64_t r = 2 * I + (s & 1);
+        const double sc = minv_sqrt[I];
+        const double2 z = (s < 2) ? L[r * ldl + col] : Y[r * ldy + col];
+        v = double2{sc * z.x, sc * z.y};
+      }
+      bufA[(c * NS + s) * N3 + i] = v;
+    }
+    __syncthreads();
+    sf_line_pass<NP, NF, 0, true>(Bt, bufA, bufB);
+    __syncthreads();
+    sf_line_pass<NP, NF, 1, true>(Bt, bufB, bufA);
+    __syncthreads();
+    sf_line_pass<NP, NF, 2, true>(Bt, bufA, bufB);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+      const int q = tid + 256 * j;
+      if (q >= N3) continue;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        if (n0 + c >= c_end) break;
+        const double cw = colw ? colw[n0 + c] : 1.0;
+        const double2 l0 = bufB[(c * NS + 0) * N3 + q], l1 = bufB[(c * NS + 1) * N3 + q];
+        const double2 y0 = bufB[(c * NS + NS - 2) * N3 + q], y1 = bufB[(c * NS + NS - 1) * N3 + q];
+        const double r00 = l0.x * y0.x + l0.y * y0.y;
+        const double r11 = l1.x * y1.x + l1.y * y1.y;
+        const double r01 = l0.x * y1.x + l0.y * y1.y, i01 = l0.x * y1.y - l0.y * y1.x;
+        const double r10 = l1.x * y0.x + l1.y * y0.y, i10 = l1.x * y0.y - l1.y * y0.x;
+        acc[j][0] += cw * (r00 + r11);
+        acc[j][1] += cw * (r01 + r10);
+        acc[j][2] += cw * (i01 - i10);
+        acc[j][3] += cw * (r00 - r11);
+      }
+    }
+    // the next gather writes bufA, which no thread reads any more
+  }
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) {
+    const int q = tid + 256 * j;
+    if (q >= N3) continue;
+    const double w = wJ ? J * w1[q % NP] * w1[(q / NP) % NP] * w1[q / N2] : 1.0;
+    double* out = partial + (((size_t)g * n_cells + e) * N3 + q) * 4;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) out[d] = w * acc[j][d];
+  }
+}
+
+template <int NP, int NS>
+static void launch_qfield_sf(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy,
+                             int n_vec, const double* colw, int wJ, double alpha, double* dV, double* dB) {
+  constexpr int CW = NS == 2 ? sf_cols(NP) : (sf_cols(NP) + 1) / 2;
+  const size_t sh = 2 * (size_t)CW * NS * NP * NP * NP * sizeof(double2);
+  if (c->mf_tab.n == 0) mf_prepare(c);
+  const int max_groups = std::max(1, cdiv(n_vec, CW));
+  const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
+  int groups = std::min(max_groups, want);
+  const int cpg = CW * cdiv(cdiv(n_vec, groups), CW);
+  groups = cdiv(n_vec, cpg);
+  const int64_t n_points = (int64_t)c->n_cells * c->nq3;
+  c->cd_partial.alloc((size_t)groups * n_points * 4);
+  const int64_t total = (int64_t)c->n_cells * groups;
+  CHFSI_CHECK(total < (int64_t)1 << 30, CHFSI_EINVAL, "quadrature-point fields: too many work items");
+  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, (double)NS / 2 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
+  hipLaunchKernelGGL((qfield_sf_kernel<NP, NS>), dim3((unsigned)(8 * ((total + 7) / 8))), dim3(256), sh, c->stream,
+                     L, ldl, Y, ldy, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->mf_tab.ptr, c->J, c->n_cells,
+                     groups, cpg, colw, wJ, c->cd_partial.ptr);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
+                     dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, alpha, dV, dB);
+  LAUNCH_CHECK();
+}
+
+// n_q = n_p: sum-factorised line passes; otherwise the general kernel below.
+template <int NS>
+static bool qfield_fast(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy, int n_vec,
+                        const double* colw, int wJ, double alpha, double* dV, double* dB) {
+  if (c->nq != c->np1) return false;
+  switch (c->np1) {
+    case 2: launch_qfield_sf<2, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 3: launch_qfield_sf<3, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 4: launch_qfield_sf<4, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 5: launch_qfield_sf<5, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 6: launch_qfield_sf<6, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 7: launch_qfield_sf<7, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 8: launch_qfield_sf<8, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    case 9: launch_qfield_sf<9, NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB); return true;
+    default: return false;
+  }
+}
+
 // Shared launcher: partial sums per (cell, column group), then the fixed-order
 // group reduction adding alpha * (sums) into (dV, dB).
 template <int NS>
 static void launch_cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy,
                                  int n_vec, const double* colw, int wJ, double alpha, double* dV, double* dB) {
+  if (qfield_fast<NS>(c, L, ldl, Y, ldy, n_vec, colw, wJ, alpha, dV, dB)) return;
   const int np1 = c->np1, nq = c->nq;
   const int maxsz = std::max(std::max(c->nloc, nq * np1 * np1), std::max(nq * nq * np1, c->nq3));
   CHFSI_CHECK(c->nq3 <= 256 * kCdMaxQ, CHFSI_EINVAL, "quadrature-point fields support n_q <= 10");

@@ -27,56 +27,11 @@
 // line, so every LDS value read feeds n_p multiply-adds.  Within a colour no
 // two cells share a node, so the scatter is a plain read-add-write.
 #include "mfma.h"
+#include "sumfact.h"
 
 namespace chfsi {
 
 namespace {
-
-// columns per workgroup: two LDS buffers of 2 spins x n_p^3 complex values per
-// column, kept near 44 KB so that three workgroups share a CU
-constexpr int mf_cols(int NP) { return NP <= 4 ? 8 : NP == 5 ? 4 : NP == 6 ? 3 : NP == 7 ? 2 : 1; }
-
-template <int NP, int DIM>
-__device__ __forceinline__ int line_base(int l) {
-  if constexpr (DIM == 0) return l * NP;                       // l = y + NP z
-  else if constexpr (DIM == 1) return (l % NP) + (l / NP) * NP * NP;   // l = x + NP z
-  else return l;                                               // l = x + NP y
-}
-
-// The two coordinates held fixed along a line (for the quadrature weights).
-template <int NP, int DIM>
-__device__ __forceinline__ void line_fixed(int l, int& i0, int& i1) {
-  i0 = l % NP;
-  i1 = l / NP;
-}
-
-// out = contraction of every (column, spin) field along DIM with the table M:
-//   FWD:  out[.. o ..] = sum_i M[i][o] in[.. i ..]   (nodes -> points, M = B)
-//   !FWD: out[.. o ..] = sum_i M[o][i] in[.. i ..]   (points -> nodes)
-template <int NP, int CW, int DIM, bool FWD>
-__device__ __forceinline__ void line_pass(const double* __restrict__ M, const double2* __restrict__ in,
-                                          double2* __restrict__ out) {
-  constexpr int N2 = NP * NP, N3 = N2 * NP;
-  constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
-  for (int t = threadIdx.x; t < N2 * 2 * CW; t += 256) {
-    const int l = t % N2, f = t / N2;
-    const int base = f * N3 + line_base<NP, DIM>(l);
-    double2 v[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) v[j] = in[base + j * S];
-#pragma unroll
-    for (int o = 0; o < NP; ++o) {
-      double re = 0.0, im = 0.0;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const double m = FWD ? M[i * NP + o] : M[o * NP + i];
-        re = fma(m, v[i].x, re);
-        im = fma(m, v[i].y, im);
-      }
-      out[base + o * S] = double2{re, im};
-    }
-  }
-}
 
 // Kinetic and k-gradient terms along DIM, added into W:
 //   G = Dq U,  W += a_d Dq^T (wJ G) - i b_d wJ G,
@@ -89,10 +44,9 @@ __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const d
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
   for (int t = threadIdx.x; t < N2 * 2 * CW; t += 256) {
     const int l = t % N2, f = t / N2;
-    const int base = f * N3 + line_base<NP, DIM>(l);
-    int i0, i1;
-    line_fixed<NP, DIM>(l, i0, i1);
-    const double wl = J * w1[i0] * w1[i1];
+    const int base = f * N3 + sf_line_base<NP, DIM>(l);
+    // the two coordinates held fixed along the line are l % NP and l / NP
+    const double wl = J * w1[l % NP] * w1[l / NP];
     double2 u[NP], g[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) u[j] = U[base + j * S];
@@ -138,7 +92,7 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
     const int32_t* __restrict__ cells, int n_in, int n_chunks, const double* __restrict__ minv_sqrt,
     const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y, int64_t ldy, int n_vec, double alpha,
     double J, double half_k2, double a0, double a1, double a2, double b0, double b1, double b2) {
-  constexpr int CW = mf_cols(NP);
+  constexpr int CW = sf_cols(NP);
   constexpr int N2 = NP * NP, N3 = N2 * NP;
   extern __shared__ double2 mf_sm[];
   double2* bufA = mf_sm;                      // [CW][2][N3]
@@ -171,11 +125,11 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
     bufA[(c * 2 + s) * N3 + i] = v;
   }
   __syncthreads();
-  line_pass<NP, CW, 0, true>(Bt, bufA, bufB);
+  sf_line_pass<NP, 2 * CW, 0, true>(Bt, bufA, bufB);
   __syncthreads();
-  line_pass<NP, CW, 1, true>(Bt, bufB, bufA);
+  sf_line_pass<NP, 2 * CW, 1, true>(Bt, bufB, bufA);
   __syncthreads();
-  line_pass<NP, CW, 2, true>(Bt, bufA, bufB);   // U in bufB
+  sf_line_pass<NP, 2 * CW, 2, true>(Bt, bufA, bufB);   // U in bufB
   __syncthreads();
 
   // potential and field terms at the points
@@ -201,11 +155,11 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
   __syncthreads();
   grad_pass<NP, CW, 2, KT>(Dq, w1, J, a2, b2, bufB, bufA);
   __syncthreads();
-  line_pass<NP, CW, 0, false>(Bt, bufA, bufB);
+  sf_line_pass<NP, 2 * CW, 0, false>(Bt, bufA, bufB);
   __syncthreads();
-  line_pass<NP, CW, 1, false>(Bt, bufB, bufA);
+  sf_line_pass<NP, 2 * CW, 1, false>(Bt, bufB, bufA);
   __syncthreads();
-  line_pass<NP, CW, 2, false>(Bt, bufA, bufB);  // y in bufB
+  sf_line_pass<NP, 2 * CW, 2, false>(Bt, bufA, bufB);  // y in bufB
   __syncthreads();
 
   // Y[rows of the cell] += alpha M^{-1/2} y
@@ -241,7 +195,7 @@ __global__ void mf_qdata_kernel(const double* __restrict__ V, const double* __re
 template <int NP, bool KT>
 void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
                  double alpha) {
-  constexpr int CW = mf_cols(NP);
+  constexpr int CW = sf_cols(NP);
   const size_t sh = 2 * (size_t)CW * 2 * NP * NP * NP * sizeof(double2);
   const int n_chunks = cdiv(n_vec, CW);
   double a[3], b[3];

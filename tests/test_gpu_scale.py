@@ -50,11 +50,12 @@ def _product_block(k, bvec, v0, n_vec, seed=0):
     return X, lam
 
 
+@pytest.mark.parametrize("form", ["cell", "matrix_free"])
 @pytest.mark.parametrize("k", [(0.0, 0.0, 0.0), (0.05, -0.03, 0.02)])
-def test_gll_kronecker_eigenvectors_full_scale(k):
+def test_gll_kronecker_eigenvectors_full_scale(k, form):
     from paper_2410_02754_amd import Operator
     n_vec, v0, bvec = 128, -0.3, np.array([0.02, -0.05, 0.08])
-    op = Operator((NC, NC, NC), (L, L, L), P, "gll", None, [k])
+    op = Operator((NC, NC, NC), (L, L, L), P, "gll", None, [k], form=form)
     V = torch.full((op.n_cells, op.nq3), v0, dtype=torch.float64, device="cuda")
     B = torch.tensor(np.tile(bvec, (op.n_cells, op.nq3, 1)), device="cuda")
     op.set_local(V, B)
@@ -65,8 +66,11 @@ def test_gll_kronecker_eigenvectors_full_scale(k):
     scale = float(np.abs(lam).max()) * float(X.abs().max())
     op.apply_H(X, Y)
     err = float((Y - X * lam_d[None, :]).abs().max()) / scale
-    print(f"[scale gll k={k}] fp64 max |H x - lam x| / (|lam| |x|) = {err:.3e}", flush=True)
+    print(f"[scale gll k={k} {form}] fp64 max |H x - lam x| / (|lam| |x|) = {err:.3e}", flush=True)
     assert err < 1e-12
+    if form == "matrix_free":
+        op.close()
+        return
     op.apply_H(X, Y, prec="mixed")
     errm = float((Y - X * lam_d[None, :]).abs().max()) / scale
     print(f"[scale gll k={k}] mixed rel residual = {errm:.3e}", flush=True)
@@ -129,3 +133,40 @@ def test_scale_workload_sampled_rows():
     print(f"[scale rows] {len(nodes)} nodes: fp64 rel err {err:.3e}, mixed {errm:.3e}", flush=True)
     assert err < 1e-12
     assert errm < 2e-6
+
+
+def test_scale_workload_sampled_rows_matrix_free():
+    """The large workload with the matrix-free local operator: rows of H_hat X
+    from the oracle at sampled nodes, and the whole product against the
+    cell-matrix path."""
+    import synth
+    from oracle import rows
+    from paper_2410_02754_amd import Operator
+    s = synth.config("scale")
+    n_vec = 128
+    X = torch.empty((s.n_dof, n_vec), dtype=torch.complex128, device="cuda")
+    Ys = {}
+    for form in ("matrix_free", "cell"):
+        op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts, form=form)
+        pts = op.quad_points().reshape(-1, 3)
+        V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+        B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+        op.set_local(V, B)
+        op.set_atoms(s.atoms)
+        del V, B, pts
+        op.fill_random(X, s.seed, n_total_cols=n_vec)
+        Ys[form] = torch.empty_like(X)
+        op.apply_H(X, Ys[form])
+        op.close()
+    scale = float(Ys["cell"].abs().max())
+    d = float((Ys["matrix_free"] - Ys["cell"]).abs().max()) / scale
+    nodes = _sample_nodes(s, np.random.default_rng(12))
+    rr = torch.tensor(np.stack([2 * nodes, 2 * nodes + 1], axis=1).ravel(), device="cuda")
+    got = Ys["matrix_free"][rr].cpu().numpy().reshape(len(nodes), 2, n_vec)
+    del X, Ys
+    ref = rows.apply_rows(s, nodes, lambda r: synth.random_rows(s.seed, r, n_vec, n_vec), synth.veff, synth.bxc)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"[scale rows matrix-free] {len(nodes)} nodes: rel err {err:.3e}; whole product vs cell path {d:.3e}",
+          flush=True)
+    assert err < 1e-12
+    assert d < 1e-12
