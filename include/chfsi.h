@@ -246,7 +246,7 @@ int chfsi_cheb_filter_backward(chfsi_ctx* ctx, int ik, const void* X_d, int64_t 
 
 /* ---- Densities from the Rayleigh-Ritz output (eqn:rho, eqn:mag), with
  * Fermi-Dirac occupations at the smearing temperature of Sec. V and the entropy
- * term of the free energy in Sec. II.C. */
+ * term of the free energy in Sec. II.B. */
 
 /* Fermi-Dirac occupations of n levels (host, float64): occ_h[i] =
  * 1 / (1 + exp((eps_h[i] - mu) / kT)) with mu chosen by bisection so that

@@ -5,7 +5,7 @@ eqn:rho and eqn:mag: rho(r) = sum_n f_n psi_n^H psi_n, m(r) = sum_n f_n psi_n^H 
 (for periodic systems the sum over n includes the Brillouin-zone average, i.e. the
 k-point weights); the occupations are Fermi-Dirac numbers at the smearing
 temperature (Sec. V: 500 K), with the Fermi level fixed by the electron count, and
-the entropy term E_ent = kT sum w [f ln f + (1 - f) ln(1 - f)] of Sec. II.C.
+the entropy term E_ent = kT sum w [f ln f + (1 - f) ln(1 - f)] of Sec. II.B.
 With psi = exp(ik.r) u the densities depend on the periodic parts u only.  The
 vectors here are the scaled blocks X = M_D^{1/2} U, so u_n(q) is the field
 sum_i N_i(r_q) (M_D^{-1/2} x_n)_i at the quadrature point.

@@ -1,5 +1,5 @@
 """chfsi_fermi_dirac (host logic of the library, no GPU) against the oracle's
-Fermi-Dirac occupations (Sec. V smearing, Sec. II.C entropy), and its argument
+Fermi-Dirac occupations (Sec. V smearing, Sec. II.B entropy), and its argument
 checks."""
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
 """Oracle pins for the densities and the Fermi-Dirac occupations (eqn:rho,
-eqn:mag; Fermi-Dirac smearing of Sec. V with the entropy term of Sec. II.C)."""
+eqn:mag; Fermi-Dirac smearing of Sec. V with the entropy term of Sec. II.B)."""
 import math
 
 import numpy as np
