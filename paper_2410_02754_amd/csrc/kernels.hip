@@ -727,20 +727,35 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
   double acc[QPT][4];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
+  constexpr int NG = N3 * NS * CW, PER = (NG + 255) / 256;
   for (int n0 = c_begin; n0 < c_end; n0 += CW) {
-    // stream s = 2 * operand + spin; column fastest so that lanes share rows
-    for (int t = tid; t < N3 * NS * CW; t += 256) {
+    // stream s = 2 * operand + spin; column fastest so that lanes share rows.
+    // All of a thread's loads are issued before any is used (addresses clamped
+    // in bounds, out-of-range elements zeroed afterwards).
+    int64_t I[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int t = min(tid + 256 * k, NG - 1);
+      I[k] = nodes[t / (NS * CW)];
+    }
+    double sc[PER];
+    double2 z[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int t = min(tid + 256 * k, NG - 1);
+      const int c = t % CW, s = (t / CW) % NS;
+      const int col = min(n0 + c, c_end - 1);
+      const int64_t r = 2 * I[k] + (s & 1);
+      sc[k] = minv_sqrt[I[k]];
+      z[k] = (s < 2) ? L[r * ldl + col] : Y[r * ldy + col];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int t = tid + 256 * k;
+      if (t >= NG) break;
       const int c = t % CW, s = (t / CW) % NS, i = t / (NS * CW);
-      const int col = n0 + c;
-      double2 v = {0.0, 0.0};
-      if (col < c_end) {
-        const int64_t I = nodes[i];
-        const int64_t r = 2 * I + (s & 1);
-        const double sc = minv_sqrt[I];
-        const double2 z = (s < 2) ? L[r * ldl + col] : Y[r * ldy + col];
-        v = double2{sc * z.x, sc * z.y};
-      }
-      bufA[(c * NS + s) * N3 + i] = v;
+      const double f = (n0 + c < c_end) ? sc[k] : 0.0;
+      bufA[(c * NS + s) * N3 + i] = double2{f * z[k].x, f * z[k].y};
     }
     __syncthreads();
     sf_line_pass<NP, NF, 0, true>(Bt, bufA, bufB);

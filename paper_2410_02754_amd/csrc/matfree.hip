@@ -36,10 +36,12 @@ namespace {
 // Kinetic and k-gradient terms along DIM, added into W:
 //   G = Dq U,  W += a_d Dq^T (wJ G) - i b_d wJ G,
 // a_d = (2/h_d)^2 / 2, b_d = k_d (2/h_d), wJ = J w_x w_y w_z at each point.
-template <int NP, int CW, int DIM, bool KT>
+// BWD: W along the line is then complete (the other directions ran before), so
+// the backward interpolation along DIM (W -> B W, table Bt) is applied in place.
+template <int NP, int CW, int DIM, bool KT, bool BWD>
 __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const double* __restrict__ w1, double J,
                                           double a_d, double b_d, const double2* __restrict__ U,
-                                          double2* __restrict__ W) {
+                                          double2* __restrict__ W, const double* __restrict__ Bt) {
   constexpr int N2 = NP * NP, N3 = N2 * NP;
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
   for (int t = threadIdx.x; t < N2 * 2 * CW; t += 256) {
@@ -66,6 +68,7 @@ __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const d
       const double s = a_d * wl * w1[q];
       fk[q] = double2{s * g[q].x, s * g[q].y};
     }
+    double2 wv[NP];
 #pragma unroll
     for (int r = 0; r < NP; ++r) {
       double2 acc = W[base + r * S];
@@ -80,57 +83,98 @@ __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const d
         acc.x = fma(s, g[r].y, acc.x);
         acc.y = fma(-s, g[r].x, acc.y);
       }
-      W[base + r * S] = acc;
+      wv[r] = acc;
+    }
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      if constexpr (BWD) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          re = fma(Bt[o * NP + i], wv[i].x, re);
+          im = fma(Bt[o * NP + i], wv[i].y, im);
+        }
+        W[base + o * S] = double2{re, im};
+      } else {
+        W[base + o * S] = wv[o];
+      }
     }
   }
 }
 
 // tab: [B: NP*NP][Dq: NP*NP][w: NP], qd: [E][NP^3] of (wJ V, wJ Bx, wJ By, wJ Bz).
+//
+// One workgroup per work item (cell of the colour, chunk of CW columns); items
+// are cell major and consecutive items run on one XCD (workgroup b on XCD b % 8),
+// so the column chunks of a cell share its rows in that XCD's L2.  Each thread
+// owns at most one (column, spin, z-line) task of the first and last phases
+// (2 CW n_p^2 <= 256 for every n_p) and issues all of that task's global loads
+// before it uses any of them.
 template <int NP, bool KT>
 __global__ __launch_bounds__(256) void mf_apply_kernel(
     const double* __restrict__ tab, const double4* __restrict__ qd, const int32_t* __restrict__ cell_nodes,
-    const int32_t* __restrict__ cells, int n_in, int n_chunks, const double* __restrict__ minv_sqrt,
+    const int32_t* __restrict__ cells, int total, int n_chunks, const double* __restrict__ minv_sqrt,
     const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y, int64_t ldy, int n_vec, double alpha,
     double J, double half_k2, double a0, double a1, double a2, double b0, double b1, double b2) {
   constexpr int CW = sf_cols(NP);
   constexpr int N2 = NP * NP, N3 = N2 * NP;
+  static_assert(2 * CW * N2 <= 256, "one edge task per thread");
   extern __shared__ double2 mf_sm[];
   double2* bufA = mf_sm;                      // [CW][2][N3]
   double2* bufB = mf_sm + CW * 2 * N3;        // [CW][2][N3]
   const double* Bt = tab;
   const double* Dq = tab + N2;
   const double* w1 = tab + 2 * N2;
-
-  // consecutive work items (the column chunks of one cell) on one XCD
-  const int total = n_in * n_chunks;
-  const int per_xcd = (total + 7) / 8;
-  const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (bid >= total) return;
-  const int e = cells[bid / n_chunks];
-  const int col0 = (bid % n_chunks) * CW;
-  const int32_t* nodes = cell_nodes + (size_t)e * N3;
   const int tid = threadIdx.x;
 
-  // gather u = M^{-1/2} x (column fastest: neighbouring lanes read one row)
-  for (int t = tid; t < N3 * 2 * CW; t += 256) {
-    const int c = t % CW, s = (t / CW) % 2, i = t / (2 * CW);
-    const int col = col0 + c;
-    double2 v = {0.0, 0.0};
-    if (col < n_vec) {
-      const int64_t I = nodes[i];
-      const double sc = minv_sqrt[I];
-      const double2 z = X[(2 * I + s) * ldx + col];
-      v = double2{sc * z.x, sc * z.y};
+  const int per_xcd = (total + 7) / 8;
+  const int item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (item >= total) return;
+  // edge task: column fastest, then spin, then the z-line (x, y), so that
+  // neighbouring lanes read one row
+  const bool edge = tid < 2 * CW * N2;
+  const int tc = tid % CW, ts = (tid / CW) % 2, tl = tid / (2 * CW);
+  const int e = cells[item / n_chunks];
+  const int col = (item % n_chunks) * CW + tc;
+  const int32_t* nodes = cell_nodes + (size_t)e * N3;
+  const bool ok = edge && col < n_vec;
+
+  // gather M^{-1/2} x along the task's z-line (addresses clamped in bounds) and
+  // interpolate along z into bufB
+  if (edge) {
+    const int cc = ok ? col : 0;
+    int64_t I[NP];
+#pragma unroll
+    for (int z = 0; z < NP; ++z) I[z] = nodes[tl + z * N2];
+    double xs[NP];
+    double2 xr[NP];
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      xs[z] = minv_sqrt[I[z]];
+      xr[z] = X[(2 * I[z] + ts) * ldx + cc];
     }
-    bufA[(c * 2 + s) * N3 + i] = v;
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      const double f = ok ? xs[z] : 0.0;
+      xr[z] = double2{f * xr[z].x, f * xr[z].y};
+    }
+    double2* out = bufB + (tc * 2 + ts) * N3 + tl;
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        re = fma(Bt[i * NP + o], xr[i].x, re);
+        im = fma(Bt[i * NP + o], xr[i].y, im);
+      }
+      out[o * N2] = double2{re, im};
+    }
   }
-  __syncthreads();
-  sf_line_pass<NP, 2 * CW, 0, true>(Bt, bufA, bufB);
-  __syncthreads();
-  sf_line_pass<NP, 2 * CW, 1, true>(Bt, bufB, bufA);
-  __syncthreads();
-  sf_line_pass<NP, 2 * CW, 2, true>(Bt, bufA, bufB);   // U in bufB
-  __syncthreads();
+  lds_barrier();
+  sf_line_pass<NP, 2 * CW, 1, true>(Bt, bufB, bufB);   // in place: a thread owns its line
+  lds_barrier();
+  sf_line_pass<NP, 2 * CW, 0, true>(Bt, bufB, bufB);   // U in bufB
+  lds_barrier();
 
   // potential and field terms at the points
   for (int t = tid; t < N3 * CW; t += 256) {
@@ -148,34 +192,46 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
     bufA[(c * 2) * N3 + q] = w0;
     bufA[(c * 2 + 1) * N3 + q] = w2;
   }
-  __syncthreads();
-  grad_pass<NP, CW, 0, KT>(Dq, w1, J, a0, b0, bufB, bufA);
-  __syncthreads();
-  grad_pass<NP, CW, 1, KT>(Dq, w1, J, a1, b1, bufB, bufA);
-  __syncthreads();
-  grad_pass<NP, CW, 2, KT>(Dq, w1, J, a2, b2, bufB, bufA);
-  __syncthreads();
-  sf_line_pass<NP, 2 * CW, 0, false>(Bt, bufA, bufB);
-  __syncthreads();
-  sf_line_pass<NP, 2 * CW, 1, false>(Bt, bufB, bufA);
-  __syncthreads();
-  sf_line_pass<NP, 2 * CW, 2, false>(Bt, bufA, bufB);  // y in bufB
-  __syncthreads();
+  lds_barrier();
+  grad_pass<NP, CW, 2, KT, false>(Dq, w1, J, a2, b2, bufB, bufA, Bt);
+  lds_barrier();
+  grad_pass<NP, CW, 1, KT, false>(Dq, w1, J, a1, b1, bufB, bufA, Bt);
+  lds_barrier();
+  grad_pass<NP, CW, 0, KT, true>(Dq, w1, J, a0, b0, bufB, bufA, Bt);   // and W -> B W along x
+  lds_barrier();
+  sf_line_pass<NP, 2 * CW, 1, false>(Bt, bufA, bufA);
+  lds_barrier();
 
-  // Y[rows of the cell] += alpha M^{-1/2} y
-  for (int t = tid; t < N3 * 2 * CW; t += 256) {
-    const int c = t % CW, s = (t / CW) % 2, i = t / (2 * CW);
-    const int col = col0 + c;
-    if (col < n_vec) {
-      const int64_t I = nodes[i];
-      const double sc = alpha * minv_sqrt[I];
-      const double2 v = bufB[(c * 2 + s) * N3 + i];
-      double2* y = Y + (2 * I + s) * ldy + col;
-      double2 o = *y;
-      o.x = fma(sc, v.x, o.x);
-      o.y = fma(sc, v.y, o.y);
-      *y = o;
+  // last backward contraction along z, then Y[rows] += alpha M^{-1/2} y (the
+  // rows' indices, factors and old values loaded together before the stores)
+  if (ok) {
+    const double2* in = bufA + (tc * 2 + ts) * N3 + tl;
+    double2 v[NP], r[NP];
+#pragma unroll
+    for (int z = 0; z < NP; ++z) v[z] = in[z * N2];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        re = fma(Bt[o * NP + i], v[i].x, re);
+        im = fma(Bt[o * NP + i], v[i].y, im);
+      }
+      r[o] = double2{re, im};
     }
+    int64_t I[NP];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) I[o] = nodes[tl + o * N2];
+    double sc[NP];
+    double2 yo[NP];
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      sc[o] = alpha * minv_sqrt[I[o]];
+      yo[o] = Y[(2 * I[o] + ts) * ldy + col];
+    }
+#pragma unroll
+    for (int o = 0; o < NP; ++o)
+      Y[(2 * I[o] + ts) * ldy + col] = double2{fma(sc[o], r[o].x, yo[o].x), fma(sc[o], r[o].y, yo[o].y)};
   }
 }
 
@@ -221,8 +277,8 @@ void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, 
     const int grid = (int)(8 * ((total + 7) / 8));
     hipLaunchKernelGGL((mf_apply_kernel<NP, KT>), dim3(grid), dim3(256), sh, c->stream, c->mf_tab.ptr,
                        reinterpret_cast<const double4*>(c->mf_qd.ptr), c->cell_nodes.ptr,
-                       c->colour_cells.ptr + c->colour_off[k], n_in, n_chunks, c->minv_sqrt.ptr, X, ldx, W, ldw,
-                       n_vec, alpha, c->J, half_k2, a[0], a[1], a[2], b[0], b[1], b[2]);
+                       c->colour_cells.ptr + c->colour_off[k], (int)total, n_chunks, c->minv_sqrt.ptr, X, ldx, W,
+                       ldw, n_vec, alpha, c->J, half_k2, a[0], a[1], a[2], b[0], b[1], b[2]);
     LAUNCH_CHECK();
   }
 }

@@ -16,6 +16,11 @@ namespace chfsi {
 // spins) for two LDS buffers of about 44 KB, so that three workgroups share a CU
 constexpr int sf_cols(int NP) { return NP <= 4 ? 8 : NP == 5 ? 4 : NP == 6 ? 3 : NP == 7 ? 2 : 1; }
 
+// Workgroup barrier for LDS hand-offs: waits for this wave's LDS operations
+// only, so global loads issued before it (a prefetch of the next work item) stay
+// in flight; __syncthreads() would wait for them as well.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // First point of line l along DIM.
 template <int NP, int DIM>
 __device__ __forceinline__ int sf_line_base(int l) {
@@ -27,9 +32,10 @@ __device__ __forceinline__ int sf_line_base(int l) {
 // out = contraction of fields 0..NF-1 along DIM with the n_p x n_p table M:
 //   FWD:  out[.. o ..] = sum_i M[i][o] in[.. i ..]   (nodes -> points with M = B)
 //   !FWD: out[.. o ..] = sum_i M[o][i] in[.. i ..]   (points -> nodes)
+// in and out may be the same buffer: a thread reads its whole line before it
+// writes it, and the lines of one pass are disjoint.
 template <int NP, int NF, int DIM, bool FWD>
-__device__ __forceinline__ void sf_line_pass(const double* __restrict__ M, const double2* __restrict__ in,
-                                             double2* __restrict__ out) {
+__device__ __forceinline__ void sf_line_pass(const double* __restrict__ M, const double2* in, double2* out) {
   constexpr int N2 = NP * NP, N3 = N2 * NP;
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
   for (int t = threadIdx.x; t < N2 * NF; t += 256) {
