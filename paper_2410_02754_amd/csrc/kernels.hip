@@ -728,27 +728,31 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
 #pragma unroll
   for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
   constexpr int NG = N3 * NS * CW, PER = (NG + 255) / 256;
+  // A thread's gather elements keep their (column offset, stream, node) over the
+  // column chunks: stream s = 2 * operand + spin, column fastest so that lanes
+  // share rows.  Rows and M^{-1/2} factors are loaded once; the next chunk's
+  // values are loaded while the current chunk runs its LDS phases (addresses
+  // clamped in bounds, out-of-range elements zeroed when stored).
+  const double2* row[PER];
+  double sc[PER];
+  int cofs[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = min(tid + 256 * k, NG - 1);
+    const int c = t % CW, s = (t / CW) % NS;
+    const int64_t I = nodes[t / (NS * CW)];
+    const int64_t r = 2 * I + (s & 1);
+    row[k] = (s < 2) ? L + r * ldl : Y + r * ldy;
+    sc[k] = minv_sqrt[I];
+    cofs[k] = c;
+  }
+  double2 z[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) z[k] = row[k][min(c_begin + cofs[k], c_end - 1)];
   for (int n0 = c_begin; n0 < c_end; n0 += CW) {
-    // stream s = 2 * operand + spin; column fastest so that lanes share rows.
-    // All of a thread's loads are issued before any is used (addresses clamped
-    // in bounds, out-of-range elements zeroed afterwards).
-    int64_t I[PER];
+    double cwv[CW];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int t = min(tid + 256 * k, NG - 1);
-      I[k] = nodes[t / (NS * CW)];
-    }
-    double sc[PER];
-    double2 z[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int t = min(tid + 256 * k, NG - 1);
-      const int c = t % CW, s = (t / CW) % NS;
-      const int col = min(n0 + c, c_end - 1);
-      const int64_t r = 2 * I[k] + (s & 1);
-      sc[k] = minv_sqrt[I[k]];
-      z[k] = (s < 2) ? L[r * ldl + col] : Y[r * ldy + col];
-    }
+    for (int c = 0; c < CW; ++c) cwv[c] = (n0 + c < c_end) ? (colw ? colw[n0 + c] : 1.0) : 0.0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int t = tid + 256 * k;
@@ -757,13 +761,17 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
       const double f = (n0 + c < c_end) ? sc[k] : 0.0;
       bufA[(c * NS + s) * N3 + i] = double2{f * z[k].x, f * z[k].y};
     }
-    __syncthreads();
+    if (n0 + CW < c_end) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) z[k] = row[k][min(n0 + CW + cofs[k], c_end - 1)];
+    }
+    lds_barrier();
     sf_line_pass<NP, NF, 0, true>(Bt, bufA, bufB);
-    __syncthreads();
+    lds_barrier();
     sf_line_pass<NP, NF, 1, true>(Bt, bufB, bufA);
-    __syncthreads();
+    lds_barrier();
     sf_line_pass<NP, NF, 2, true>(Bt, bufA, bufB);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
       const int q = tid + 256 * j;
@@ -771,7 +779,7 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
 #pragma unroll
       for (int c = 0; c < CW; ++c) {
         if (n0 + c >= c_end) break;
-        const double cw = colw ? colw[n0 + c] : 1.0;
+        const double cw = cwv[c];
         const double2 l0 = bufB[(c * NS + 0) * N3 + q], l1 = bufB[(c * NS + 1) * N3 + q];
         const double2 y0 = bufB[(c * NS + NS - 2) * N3 + q], y1 = bufB[(c * NS + NS - 1) * N3 + q];
         const double r00 = l0.x * y0.x + l0.y * y0.y;
