@@ -697,24 +697,33 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
   }
 }
 
-// The same sums with n_q = n_p: the gathered fields are interpolated by line
-// passes (one thread per line of a field, sf_line_pass), CW columns of NS
-// streams at a time.  tab = [B: n_p^2][Dq: n_p^2][w: n_p] (matrix-free tables).
+// The same sums with n_q = n_p by sum factorisation.  A workgroup of 512
+// threads owns one cell and a group of columns, and walks the group in chunks of
+// CW columns of NS streams (NF = NS CW fields, one LDS buffer of n_p^3 complex
+// values per field).  Per chunk each thread loads the z-lines of its
+// (column, stream, line) tasks straight into registers (column fastest: eight
+// columns are one 128-byte line of a row), interpolates along z there, and the y
+// and x passes run in place in LDS; the next chunk's z-lines are loaded while the
+// current chunk runs its LDS phases (LDS-only barriers).  Whole lines per row and
+// chunk keep the block's HBM traffic at one read.  tab = [B: n_p^2][Dq: n_p^2][w: n_p].
 // Work item bid -> cell bid % n_cells, column group bid / n_cells, neighbouring
 // cells (which share face nodes) on one XCD.
+constexpr int kQfThreads = 512;
+constexpr int qf_fields(int NP) { return NP <= 8 ? 16 : 8; }
+
 template <int NP, int NS>
-__global__ __launch_bounds__(256) void qfield_sf_kernel(
+__global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
     const double2* __restrict__ L, int64_t ldl, const double2* __restrict__ Y, int64_t ldy, int n_vec,
     const int32_t* __restrict__ cell_nodes, const double* __restrict__ minv_sqrt, const double* __restrict__ tab,
     double J, int n_cells, int n_groups, int cols_per_group, const double* __restrict__ colw, int wJ,
     double* __restrict__ partial) {
-  constexpr int CW = NS == 2 ? sf_cols(NP) : (sf_cols(NP) + 1) / 2;
-  constexpr int NF = CW * NS;
+  constexpr int NT = kQfThreads;
+  constexpr int NF = qf_fields(NP), CW = NF / NS;
   constexpr int N2 = NP * NP, N3 = N2 * NP;
-  constexpr int QPT = (N3 + 255) / 256;
+  constexpr int NTASK = NF * N2, TPT = (NTASK + NT - 1) / NT;
+  constexpr int QPT = (N3 + NT - 1) / NT;
   extern __shared__ double2 qf_sm[];
-  double2* bufA = qf_sm;              // [CW][NS][N3]
-  double2* bufB = qf_sm + NF * N3;    // [CW][NS][N3]
+  double2* buf = qf_sm;                 // [CW][NS][N3]
   const double* Bt = tab;
   const double* w1 = tab + 2 * N2;
   const int total = n_cells * n_groups;
@@ -724,64 +733,83 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
   const int e = bid % n_cells, g = bid / n_cells, tid = threadIdx.x;
   const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
   const int32_t* nodes = cell_nodes + (size_t)e * N3;
+
+  // the thread's tasks: (column offset c, stream s = 2 operand + spin, z-line l);
+  // row pointers and M^{-1/2} factors are fixed over the chunks
+  const double2* row[TPT][NP];
+  double sc[TPT][NP];
+  int tcol[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int t = min(tid + NT * k, NTASK - 1);
+    const int c = t % CW, s = (t / CW) % NS, l = t / (CW * NS);
+    tcol[k] = c;
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      const int64_t I = nodes[l + z * N2];
+      const int64_t r = 2 * I + (s & 1);
+      row[k][z] = (s < 2) ? L + r * ldl : Y + r * ldy;
+      sc[k][z] = minv_sqrt[I];
+    }
+  }
+  double2 zv[TPT][NP];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k)
+#pragma unroll
+    for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(c_begin + tcol[k], c_end - 1)];
+
   double acc[QPT][4];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
-  constexpr int NG = N3 * NS * CW, PER = (NG + 255) / 256;
-  // A thread's gather elements keep their (column offset, stream, node) over the
-  // column chunks: stream s = 2 * operand + spin, column fastest so that lanes
-  // share rows.  Rows and M^{-1/2} factors are loaded once; the next chunk's
-  // values are loaded while the current chunk runs its LDS phases (addresses
-  // clamped in bounds, out-of-range elements zeroed when stored).
-  const double2* row[PER];
-  double sc[PER];
-  int cofs[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int t = min(tid + 256 * k, NG - 1);
-    const int c = t % CW, s = (t / CW) % NS;
-    const int64_t I = nodes[t / (NS * CW)];
-    const int64_t r = 2 * I + (s & 1);
-    row[k] = (s < 2) ? L + r * ldl : Y + r * ldy;
-    sc[k] = minv_sqrt[I];
-    cofs[k] = c;
-  }
-  double2 z[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) z[k] = row[k][min(c_begin + cofs[k], c_end - 1)];
   for (int n0 = c_begin; n0 < c_end; n0 += CW) {
     double cwv[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) cwv[c] = (n0 + c < c_end) ? (colw ? colw[n0 + c] : 1.0) : 0.0;
+    // interpolation along z in registers (zero past the last column)
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int t = tid + 256 * k;
-      if (t >= NG) break;
-      const int c = t % CW, s = (t / CW) % NS, i = t / (NS * CW);
-      const double f = (n0 + c < c_end) ? sc[k] : 0.0;
-      bufA[(c * NS + s) * N3 + i] = double2{f * z[k].x, f * z[k].y};
+    for (int k = 0; k < TPT; ++k) {
+      const int t = tid + NT * k;
+      if (t >= NTASK) break;
+      const int c = t % CW, s = (t / CW) % NS, l = t / (CW * NS);
+      const bool ok = n0 + c < c_end;
+      double2 u[NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const double f = ok ? sc[k][i] : 0.0;
+        u[i] = double2{f * zv[k][i].x, f * zv[k][i].y};
+      }
+      double2* out = buf + (c * NS + s) * N3 + l;
+#pragma unroll
+      for (int o = 0; o < NP; ++o) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          re = fma(Bt[i * NP + o], u[i].x, re);
+          im = fma(Bt[i * NP + o], u[i].y, im);
+        }
+        out[o * N2] = double2{re, im};
+      }
     }
     if (n0 + CW < c_end) {
 #pragma unroll
-      for (int k = 0; k < PER; ++k) z[k] = row[k][min(n0 + CW + cofs[k], c_end - 1)];
+      for (int k = 0; k < TPT; ++k)
+#pragma unroll
+        for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(n0 + CW + tcol[k], c_end - 1)];
     }
     lds_barrier();
-    sf_line_pass<NP, NF, 0, true>(Bt, bufA, bufB);
+    sf_line_pass<NP, NF, 1, true, NT>(Bt, buf, buf);
     lds_barrier();
-    sf_line_pass<NP, NF, 1, true>(Bt, bufB, bufA);
-    lds_barrier();
-    sf_line_pass<NP, NF, 2, true>(Bt, bufA, bufB);
+    sf_line_pass<NP, NF, 0, true, NT>(Bt, buf, buf);
     lds_barrier();
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
-      const int q = tid + 256 * j;
+      const int q = tid + NT * j;
       if (q >= N3) continue;
 #pragma unroll
       for (int c = 0; c < CW; ++c) {
-        if (n0 + c >= c_end) break;
         const double cw = cwv[c];
-        const double2 l0 = bufB[(c * NS + 0) * N3 + q], l1 = bufB[(c * NS + 1) * N3 + q];
-        const double2 y0 = bufB[(c * NS + NS - 2) * N3 + q], y1 = bufB[(c * NS + NS - 1) * N3 + q];
+        const double2 l0 = buf[(c * NS + 0) * N3 + q], l1 = buf[(c * NS + 1) * N3 + q];
+        const double2 y0 = buf[(c * NS + NS - 2) * N3 + q], y1 = buf[(c * NS + NS - 1) * N3 + q];
         const double r00 = l0.x * y0.x + l0.y * y0.y;
         const double r11 = l1.x * y1.x + l1.y * y1.y;
         const double r01 = l0.x * y1.x + l0.y * y1.y, i01 = l0.x * y1.y - l0.y * y1.x;
@@ -792,11 +820,11 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
         acc[j][3] += cw * (r00 - r11);
       }
     }
-    // the next gather writes bufA, which no thread reads any more
+    lds_barrier();   // the next chunk overwrites the buffer
   }
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
-    const int q = tid + 256 * j;
+    const int q = tid + NT * j;
     if (q >= N3) continue;
     const double w = wJ ? J * w1[q % NP] * w1[(q / NP) % NP] * w1[q / N2] : 1.0;
     double* out = partial + (((size_t)g * n_cells + e) * N3 + q) * 4;
@@ -808,8 +836,8 @@ __global__ __launch_bounds__(256) void qfield_sf_kernel(
 template <int NP, int NS>
 static void launch_qfield_sf(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy,
                              int n_vec, const double* colw, int wJ, double alpha, double* dV, double* dB) {
-  constexpr int CW = NS == 2 ? sf_cols(NP) : (sf_cols(NP) + 1) / 2;
-  const size_t sh = 2 * (size_t)CW * NS * NP * NP * NP * sizeof(double2);
+  constexpr int CW = qf_fields(NP) / NS;
+  const size_t sh = (size_t)qf_fields(NP) * NP * NP * NP * sizeof(double2);
   if (c->mf_tab.n == 0) mf_prepare(c);
   const int max_groups = std::max(1, cdiv(n_vec, CW));
   const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
@@ -821,9 +849,9 @@ static void launch_qfield_sf(chfsi_ctx* c, const double2* L, int64_t ldl, const 
   const int64_t total = (int64_t)c->n_cells * groups;
   CHFSI_CHECK(total < (int64_t)1 << 30, CHFSI_EINVAL, "quadrature-point fields: too many work items");
   StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, (double)NS / 2 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
-  hipLaunchKernelGGL((qfield_sf_kernel<NP, NS>), dim3((unsigned)(8 * ((total + 7) / 8))), dim3(256), sh, c->stream,
-                     L, ldl, Y, ldy, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->mf_tab.ptr, c->J, c->n_cells,
-                     groups, cpg, colw, wJ, c->cd_partial.ptr);
+  hipLaunchKernelGGL((qfield_sf_kernel<NP, NS>), dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kQfThreads), sh,
+                     c->stream, L, ldl, Y, ldy, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->mf_tab.ptr, c->J,
+                     c->n_cells, groups, cpg, colw, wJ, c->cd_partial.ptr);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
                      dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, alpha, dV, dB);

@@ -2,7 +2,7 @@
 // the matrix-free operator and the quadrature-point field kernels.
 //
 // A cell field holds n_p^3 complex values at the points x + n_p (y + n_p z)
-// (nodes or quadrature points, n_q = n_p).  A workgroup of 256 threads holds NF
+// (nodes or quadrature points, n_q = n_p).  A workgroup of NT threads holds NF
 // such fields in LDS; a pass along direction DIM gives each thread one line
 // (n_p values along DIM, the other two coordinates fixed) of one field, so every
 // value read from LDS feeds n_p multiply-adds.
@@ -34,11 +34,11 @@ __device__ __forceinline__ int sf_line_base(int l) {
 //   !FWD: out[.. o ..] = sum_i M[o][i] in[.. i ..]   (points -> nodes)
 // in and out may be the same buffer: a thread reads its whole line before it
 // writes it, and the lines of one pass are disjoint.
-template <int NP, int NF, int DIM, bool FWD>
+template <int NP, int NF, int DIM, bool FWD, int NT = 256>
 __device__ __forceinline__ void sf_line_pass(const double* __restrict__ M, const double2* in, double2* out) {
   constexpr int N2 = NP * NP, N3 = N2 * NP;
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
-  for (int t = threadIdx.x; t < N2 * NF; t += 256) {
+  for (int t = threadIdx.x; t < N2 * NF; t += NT) {
     const int l = t % N2, f = t / N2;
     const int base = f * N3 + sf_line_base<NP, DIM>(l);
     double2 v[NP];
