@@ -135,9 +135,10 @@ enum chfsi_form { CHFSI_FORM_CELL_MATRIX = 0, CHFSI_FORM_MATRIX_FREE = 1 };
  * nodes.  Only w_q J (V, B) per quadrature point is stored (32 B per point
  * instead of about 4 (2 n_p^3)^2 x 8 B of matrices per cell).  Same quadrature,
  * so the result equals the cell-matrix product up to rounding.  Needs
- * n_q = p + 1 (GL with n_q = p + 1, or GLL) and FP64 throughout: with this
- * form, CHFSI_PREC_MIXED requests return CHFSI_EINVAL and chfsi_batch_create
- * rejects the context.  The call clears the local operator (CHFSI_ESTATE until
+ * n_q = p + 1 (GL with n_q = p + 1, or GLL).  CHFSI_PREC_MIXED runs the same
+ * contractions in FP32 (tables, quadrature data and fields in FP32, rows
+ * converted on gather and added into the FP64 output).  chfsi_batch_create
+ * rejects contexts of this form.  The call clears the local operator (CHFSI_ESTATE until
  * the next chfsi_set_local builds it in the chosen form).  CHFSI_EINVAL for an
  * unknown form or unsupported mesh. */
 int chfsi_set_apply_form(chfsi_ctx* ctx, int form);

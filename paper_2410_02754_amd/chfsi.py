@@ -73,7 +73,7 @@ class Operator:
             self.set_form(form)
 
     def set_form(self, form: str):
-        """"cell" (stored cell matrices) or "matrix_free" (sum factorisation, FP64);
+        """"cell" (stored cell matrices) or "matrix_free" (sum factorisation);
         the local operator must be set again afterwards."""
         if form not in FORMS:
             raise ValueError(f"form must be one of {sorted(FORMS)}")

@@ -52,10 +52,6 @@ static void require_operator(const chfsi_ctx* c) {
   CHFSI_CHECK(c->have_local, CHFSI_ESTATE, "chfsi_set_local has not been called");
 }
 
-static void require_prec_form(const chfsi_ctx* c, int prec) {
-  CHFSI_CHECK(!(c->form == CHFSI_FORM_MATRIX_FREE && prec == CHFSI_PREC_MIXED), CHFSI_EINVAL,
-              "the matrix-free form is FP64 only");
-}
 
 extern "C" {
 
@@ -161,6 +157,7 @@ int chfsi_set_apply_form(chfsi_ctx* c, int form) {
     kp->cell32.release();
   }
   c->mf_qd.release();
+  c->mf_qd32.release();
   c->form = form;
   c->have_local = false;
   API_END(c)
@@ -241,7 +238,6 @@ int chfsi_apply_H(chfsi_ctx* c, int ik, const void* X, int64_t ldx, void* Y, int
   check_block(c, Y, ldy, n_vec, "Y");
   CHFSI_CHECK(X != Y, CHFSI_EINVAL, "X and Y must be distinct");
   CHFSI_CHECK(prec == CHFSI_PREC_FP64 || prec == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
-  require_prec_form(c, prec);
   KPoint& kp = kpoint(c, ik);
   apply_H(c, kp, (const double2*)X, ldx, (double2*)Y, ldy, n_vec, prec, 1.0, 0.0, 0.0);
   API_END(c)
@@ -259,7 +255,6 @@ int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, in
   CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
               "filter bounds must satisfy a0 < a < b");
   CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
-  require_prec_form(c, prec_mode);
   KPoint& kp = kpoint(c, ik);
   const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
   const double sigma1 = e / (a0 - cc);
@@ -321,7 +316,6 @@ int chfsi_cheb_filter_resid(chfsi_ctx* c, int ik, void* X, int64_t ldx, const vo
   CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
               "filter bounds must satisfy a0 < a < b");
   CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
-  require_prec_form(c, prec_mode);
   KPoint& kp = kpoint(c, ik);
   const int m = degree, n = n_vec;
   const int64_t rows = 2 * c->n_nodes;

@@ -198,6 +198,7 @@ struct chfsi_ctx {
   int form = 0;
   chfsi::DevBuf<double> mf_tab;               // [B: np1^2][Dq: np1^2][w: np1]
   chfsi::DevBuf<double> mf_qd;                // [E][nq^3][4]: w_q J (V, Bx, By, Bz)
+  chfsi::DevBuf<float> mf_tab32, mf_qd32;     // FP32 copies for mixed precision
   // stage timing
   bool stats_on = false;
   std::vector<chfsi::StageRec> pending;
@@ -260,8 +261,8 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
 bool mf_supported(const chfsi_ctx* c);
 void mf_prepare(chfsi_ctx* c);
 void mf_set_local(chfsi_ctx* c, const double* V, const double* B);
-void launch_mf_products(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-                        int n_vec, double alpha);
+void launch_mf_products(chfsi_ctx* c, const KPoint& kp, int prec, const double2* X, int64_t ldx, double2* W,
+                        int64_t ldw, int n_vec, double alpha);
 void densities(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* occ_d, double* rho,
                double* mag);
 void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,

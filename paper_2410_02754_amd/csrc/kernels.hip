@@ -488,8 +488,7 @@ void apply_H3(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* 
                                  Rs, ldr, rscale);
   }
   if (c->form == CHFSI_FORM_MATRIX_FREE) {
-    CHFSI_CHECK(prec == CHFSI_PREC_FP64, CHFSI_EINVAL, "the matrix-free form is FP64 only");
-    launch_mf_products(c, kp, X, ldx, W, ldw, n_vec, alpha);
+    launch_mf_products(c, kp, prec, X, ldx, W, ldw, n_vec, alpha);
   } else {
     launch_cell_products(c, kp, prec, X, ldx, W, ldw, n_vec, alpha);
   }

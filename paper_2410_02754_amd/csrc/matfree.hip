@@ -20,8 +20,11 @@
 // n_p^4 complex-by-real multiply-adds per spin, against 4 (2 n_p^3)^2 for the
 // dense cell product, and no cell matrices are stored.
 //
-// Launch: one workgroup of 256 threads per (cell of one colour, chunk of CW
-// columns).  Both spins of CW columns live in two LDS buffers of n_p^3 complex
+// FP64, or FP32 (mixed precision: tables, quadrature data, LDS fields and
+// arithmetic in FP32, rows converted on gather and added into the FP64 output).
+//
+// Launch: one workgroup of 256 (FP64) or 512 (FP32) threads per (cell of one
+// colour, chunk of CW columns).  Both spins of CW columns live in two LDS buffers of n_p^3 complex
 // values per field; each thread owns one line (along the pass direction) of
 // one (column, spin) field, keeps it in registers and writes the contracted
 // line, so every LDS value read feeds n_p multiply-adds.  Within a colour no
@@ -33,45 +36,62 @@ namespace chfsi {
 
 namespace {
 
+template <class T> struct MfT;
+template <> struct MfT<double> {
+  typedef double2 C2;
+  typedef double4 Q4;
+  static constexpr int NT = 256;
+};
+template <> struct MfT<float> {
+  typedef float2 C2;
+  typedef float4 Q4;
+  static constexpr int NT = 512;
+};
+// columns per workgroup: the same LDS bytes in both precisions
+template <class T>
+constexpr int mf_cw(int NP) { return sizeof(T) == 8 ? sf_cols(NP) : 2 * sf_cols(NP); }
+
 // Kinetic and k-gradient terms along DIM, added into W:
 //   G = Dq U,  W += a_d Dq^T (wJ G) - i b_d wJ G,
 // a_d = (2/h_d)^2 / 2, b_d = k_d (2/h_d), wJ = J w_x w_y w_z at each point.
 // BWD: W along the line is then complete (the other directions ran before), so
 // the backward interpolation along DIM (W -> B W, table Bt) is applied in place.
-template <int NP, int CW, int DIM, bool KT, bool BWD>
-__device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const double* __restrict__ w1, double J,
-                                          double a_d, double b_d, const double2* __restrict__ U,
-                                          double2* __restrict__ W, const double* __restrict__ Bt) {
+template <class T, int NP, int CW, int DIM, bool KT, bool BWD>
+__device__ __forceinline__ void grad_pass(const T* __restrict__ Dq, const T* __restrict__ w1, T J, T a_d, T b_d,
+                                          const typename MfT<T>::C2* __restrict__ U,
+                                          typename MfT<T>::C2* __restrict__ W, const T* __restrict__ Bt) {
+  typedef typename MfT<T>::C2 C2;
+  constexpr int NT = MfT<T>::NT;
   constexpr int N2 = NP * NP, N3 = N2 * NP;
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
-  for (int t = threadIdx.x; t < N2 * 2 * CW; t += 256) {
+  for (int t = threadIdx.x; t < N2 * 2 * CW; t += NT) {
     const int l = t % N2, f = t / N2;
     const int base = f * N3 + sf_line_base<NP, DIM>(l);
     // the two coordinates held fixed along the line are l % NP and l / NP
-    const double wl = J * w1[l % NP] * w1[l / NP];
-    double2 u[NP], g[NP];
+    const T wl = J * w1[l % NP] * w1[l / NP];
+    C2 u[NP], g[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) u[j] = U[base + j * S];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      double re = 0.0, im = 0.0;
+      T re = 0, im = 0;
 #pragma unroll
       for (int r = 0; r < NP; ++r) {
         re = fma(Dq[q * NP + r], u[r].x, re);
         im = fma(Dq[q * NP + r], u[r].y, im);
       }
-      g[q] = double2{re, im};
+      g[q] = C2{re, im};
     }
-    double2 fk[NP];
+    C2 fk[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      const double s = a_d * wl * w1[q];
-      fk[q] = double2{s * g[q].x, s * g[q].y};
+      const T s = a_d * wl * w1[q];
+      fk[q] = C2{s * g[q].x, s * g[q].y};
     }
-    double2 wv[NP];
+    C2 wv[NP];
 #pragma unroll
     for (int r = 0; r < NP; ++r) {
-      double2 acc = W[base + r * S];
+      C2 acc = W[base + r * S];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         acc.x = fma(Dq[q * NP + r], fk[q].x, acc.x);
@@ -79,7 +99,7 @@ __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const d
       }
       if constexpr (KT) {
         // -i b wJ g = b wJ g.y - i b wJ g.x
-        const double s = b_d * wl * w1[r];
+        const T s = b_d * wl * w1[r];
         acc.x = fma(s, g[r].y, acc.x);
         acc.y = fma(-s, g[r].x, acc.y);
       }
@@ -88,13 +108,13 @@ __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const d
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
       if constexpr (BWD) {
-        double re = 0.0, im = 0.0;
+        T re = 0, im = 0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
           re = fma(Bt[o * NP + i], wv[i].x, re);
           im = fma(Bt[o * NP + i], wv[i].y, im);
         }
-        W[base + o * S] = double2{re, im};
+        W[base + o * S] = C2{re, im};
       } else {
         W[base + o * S] = wv[o];
       }
@@ -102,29 +122,33 @@ __device__ __forceinline__ void grad_pass(const double* __restrict__ Dq, const d
   }
 }
 
-// tab: [B: NP*NP][Dq: NP*NP][w: NP], qd: [E][NP^3] of (wJ V, wJ Bx, wJ By, wJ Bz).
+// tab: [B: NP*NP][Dq: NP*NP][w: NP], qd: [E][NP^3] of (wJ V, wJ Bx, wJ By, wJ Bz),
+// both in the arithmetic type T.
 //
 // One workgroup per work item (cell of the colour, chunk of CW columns); items
 // are cell major and consecutive items run on one XCD (workgroup b on XCD b % 8),
 // so the column chunks of a cell share its rows in that XCD's L2.  Each thread
 // owns at most one (column, spin, z-line) task of the first and last phases
-// (2 CW n_p^2 <= 256 for every n_p) and issues all of that task's global loads
+// (2 CW n_p^2 <= NT for every n_p) and issues all of that task's global loads
 // before it uses any of them.
-template <int NP, bool KT>
-__global__ __launch_bounds__(256) void mf_apply_kernel(
-    const double* __restrict__ tab, const double4* __restrict__ qd, const int32_t* __restrict__ cell_nodes,
+template <class T, int NP, bool KT>
+__global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
+    const T* __restrict__ tab, const typename MfT<T>::Q4* __restrict__ qd, const int32_t* __restrict__ cell_nodes,
     const int32_t* __restrict__ cells, int total, int n_chunks, const double* __restrict__ minv_sqrt,
     const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y, int64_t ldy, int n_vec, double alpha,
-    double J, double half_k2, double a0, double a1, double a2, double b0, double b1, double b2) {
-  constexpr int CW = sf_cols(NP);
+    T J, T half_k2, T a0, T a1, T a2, T b0, T b1, T b2) {
+  typedef typename MfT<T>::C2 C2;
+  typedef typename MfT<T>::Q4 Q4;
+  constexpr int NT = MfT<T>::NT;
+  constexpr int CW = mf_cw<T>(NP);
   constexpr int N2 = NP * NP, N3 = N2 * NP;
-  static_assert(2 * CW * N2 <= 256, "one edge task per thread");
-  extern __shared__ double2 mf_sm[];
-  double2* bufA = mf_sm;                      // [CW][2][N3]
-  double2* bufB = mf_sm + CW * 2 * N3;        // [CW][2][N3]
-  const double* Bt = tab;
-  const double* Dq = tab + N2;
-  const double* w1 = tab + 2 * N2;
+  static_assert(2 * CW * N2 <= NT, "one edge task per thread");
+  extern __shared__ double2 mf_sm_raw[];
+  C2* bufA = reinterpret_cast<C2*>(mf_sm_raw);   // [CW][2][N3]
+  C2* bufB = bufA + CW * 2 * N3;                 // [CW][2][N3]
+  const T* Bt = tab;
+  const T* Dq = tab + N2;
+  const T* w1 = tab + 2 * N2;
   const int tid = threadIdx.x;
 
   const int per_xcd = (total + 7) / 8;
@@ -153,38 +177,39 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
       xs[z] = minv_sqrt[I[z]];
       xr[z] = X[(2 * I[z] + ts) * ldx + cc];
     }
+    C2 u[NP];
 #pragma unroll
     for (int z = 0; z < NP; ++z) {
       const double f = ok ? xs[z] : 0.0;
-      xr[z] = double2{f * xr[z].x, f * xr[z].y};
+      u[z] = C2{(T)(f * xr[z].x), (T)(f * xr[z].y)};
     }
-    double2* out = bufB + (tc * 2 + ts) * N3 + tl;
+    C2* out = bufB + (tc * 2 + ts) * N3 + tl;
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
-      double re = 0.0, im = 0.0;
+      T re = 0, im = 0;
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        re = fma(Bt[i * NP + o], xr[i].x, re);
-        im = fma(Bt[i * NP + o], xr[i].y, im);
+        re = fma(Bt[i * NP + o], u[i].x, re);
+        im = fma(Bt[i * NP + o], u[i].y, im);
       }
-      out[o * N2] = double2{re, im};
+      out[o * N2] = C2{re, im};
     }
   }
   lds_barrier();
-  sf_line_pass<NP, 2 * CW, 1, true>(Bt, bufB, bufB);   // in place: a thread owns its line
+  sf_line_pass<NP, 2 * CW, 1, true, NT, T>(Bt, bufB, bufB);   // in place: a thread owns its line
   lds_barrier();
-  sf_line_pass<NP, 2 * CW, 0, true>(Bt, bufB, bufB);   // U in bufB
+  sf_line_pass<NP, 2 * CW, 0, true, NT, T>(Bt, bufB, bufB);   // U in bufB
   lds_barrier();
 
   // potential and field terms at the points
-  for (int t = tid; t < N3 * CW; t += 256) {
+  for (int t = tid; t < N3 * CW; t += NT) {
     const int q = t % N3, c = t / N3;
-    const double wj = J * w1[q % NP] * w1[(q / NP) % NP] * w1[q / N2];
-    const double4 d = qd[(size_t)e * N3 + q];
-    const double2 u0 = bufB[(c * 2) * N3 + q], u1 = bufB[(c * 2 + 1) * N3 + q];
-    const double s = d.x + half_k2 * wj;
+    const T wj = J * w1[q % NP] * w1[(q / NP) % NP] * w1[q / N2];
+    const Q4 d = qd[(size_t)e * N3 + q];
+    const C2 u0 = bufB[(c * 2) * N3 + q], u1 = bufB[(c * 2 + 1) * N3 + q];
+    const T s = d.x + half_k2 * wj;
     // up:   (s + Bz) u0 + (Bx - i By) u1;  down: (s - Bz) u1 + (Bx + i By) u0
-    double2 w0, w2;
+    C2 w0, w2;
     w0.x = (s + d.w) * u0.x + d.y * u1.x + d.z * u1.y;
     w0.y = (s + d.w) * u0.y + d.y * u1.y - d.z * u1.x;
     w2.x = (s - d.w) * u1.x + d.y * u0.x - d.z * u0.y;
@@ -193,31 +218,32 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
     bufA[(c * 2 + 1) * N3 + q] = w2;
   }
   lds_barrier();
-  grad_pass<NP, CW, 2, KT, false>(Dq, w1, J, a2, b2, bufB, bufA, Bt);
+  grad_pass<T, NP, CW, 2, KT, false>(Dq, w1, J, a2, b2, bufB, bufA, Bt);
   lds_barrier();
-  grad_pass<NP, CW, 1, KT, false>(Dq, w1, J, a1, b1, bufB, bufA, Bt);
+  grad_pass<T, NP, CW, 1, KT, false>(Dq, w1, J, a1, b1, bufB, bufA, Bt);
   lds_barrier();
-  grad_pass<NP, CW, 0, KT, true>(Dq, w1, J, a0, b0, bufB, bufA, Bt);   // and W -> B W along x
+  grad_pass<T, NP, CW, 0, KT, true>(Dq, w1, J, a0, b0, bufB, bufA, Bt);   // and W -> B W along x
   lds_barrier();
-  sf_line_pass<NP, 2 * CW, 1, false>(Bt, bufA, bufA);
+  sf_line_pass<NP, 2 * CW, 1, false, NT, T>(Bt, bufA, bufA);
   lds_barrier();
 
   // last backward contraction along z, then Y[rows] += alpha M^{-1/2} y (the
   // rows' indices, factors and old values loaded together before the stores)
   if (ok) {
-    const double2* in = bufA + (tc * 2 + ts) * N3 + tl;
-    double2 v[NP], r[NP];
+    const C2* in = bufA + (tc * 2 + ts) * N3 + tl;
+    C2 v[NP];
+    double2 r[NP];
 #pragma unroll
     for (int z = 0; z < NP; ++z) v[z] = in[z * N2];
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
-      double re = 0.0, im = 0.0;
+      T re = 0, im = 0;
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         re = fma(Bt[o * NP + i], v[i].x, re);
         im = fma(Bt[o * NP + i], v[i].y, im);
       }
-      r[o] = double2{re, im};
+      r[o] = double2{(double)re, (double)im};
     }
     int64_t I[NP];
 #pragma unroll
@@ -235,32 +261,45 @@ __global__ __launch_bounds__(256) void mf_apply_kernel(
   }
 }
 
-// qd[e][q] = w_q J (V, Bx, By, Bz)
+// qd[e][q] = w_q J (V, Bx, By, Bz), in FP64 and FP32
 __global__ void mf_qdata_kernel(const double* __restrict__ V, const double* __restrict__ B,
                                 const double* __restrict__ w1, double J, int nq, int64_t n_points,
-                                double4* __restrict__ qd) {
+                                double4* __restrict__ qd, float4* __restrict__ qd32) {
   const int nq3 = nq * nq * nq;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_points;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int q = (int)(p % nq3);
     const double wj = J * w1[q % nq] * w1[(q / nq) % nq] * w1[q / (nq * nq)];
-    qd[p] = double4{wj * V[p], wj * B[3 * p], wj * B[3 * p + 1], wj * B[3 * p + 2]};
+    const double4 v = double4{wj * V[p], wj * B[3 * p], wj * B[3 * p + 1], wj * B[3 * p + 2]};
+    qd[p] = v;
+    qd32[p] = float4{(float)v.x, (float)v.y, (float)v.z, (float)v.w};
   }
 }
 
-template <int NP, bool KT>
+template <class T, int NP, bool KT>
 void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
                  double alpha) {
-  constexpr int CW = sf_cols(NP);
-  const size_t sh = 2 * (size_t)CW * 2 * NP * NP * NP * sizeof(double2);
+  typedef typename MfT<T>::C2 C2;
+  typedef typename MfT<T>::Q4 Q4;
+  constexpr int CW = mf_cw<T>(NP);
+  const size_t sh = 2 * (size_t)CW * 2 * NP * NP * NP * sizeof(C2);
   const int n_chunks = cdiv(n_vec, CW);
-  double a[3], b[3];
+  T a[3], b[3];
   for (int d = 0; d < 3; ++d) {
     const double sd = 2.0 / c->h[d];
-    a[d] = 0.5 * sd * sd;
-    b[d] = kp.k[d] * sd;
+    a[d] = (T)(0.5 * sd * sd);
+    b[d] = (T)(kp.k[d] * sd);
   }
-  const double half_k2 = 0.5 * (kp.k[0] * kp.k[0] + kp.k[1] * kp.k[1] + kp.k[2] * kp.k[2]);
+  const T half_k2 = (T)(0.5 * (kp.k[0] * kp.k[0] + kp.k[1] * kp.k[1] + kp.k[2] * kp.k[2]));
+  const T* tab = nullptr;
+  const Q4* qd = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    tab = c->mf_tab.ptr;
+    qd = reinterpret_cast<const Q4*>(c->mf_qd.ptr);
+  } else {
+    tab = c->mf_tab32.ptr;
+    qd = reinterpret_cast<const Q4*>(c->mf_qd32.ptr);
+  }
   const double np3 = (double)NP * NP * NP;
   for (int k = 0; k < c->n_colours; ++k) {
     const int n_in = c->colour_off[k + 1] - c->colour_off[k];
@@ -273,21 +312,26 @@ void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, 
     const double flops = 8.0 * n2 * n2 * n_vec * n_in;
     const double exec = 96.0 * np3 * NP * (double)n_vec * n_in;
     const double bytes = (double)n_in * 3.0 * c->nloc * 2.0 * n_vec * sizeof(double2);
-    StageTimer tm(c, CHFSI_STAGE_CELL_FP64, flops, exec, bytes);
+    StageTimer tm(c, sizeof(T) == 8 ? CHFSI_STAGE_CELL_FP64 : CHFSI_STAGE_CELL_FP32, flops, exec, bytes);
     const int grid = (int)(8 * ((total + 7) / 8));
-    hipLaunchKernelGGL((mf_apply_kernel<NP, KT>), dim3(grid), dim3(256), sh, c->stream, c->mf_tab.ptr,
-                       reinterpret_cast<const double4*>(c->mf_qd.ptr), c->cell_nodes.ptr,
-                       c->colour_cells.ptr + c->colour_off[k], (int)total, n_chunks, c->minv_sqrt.ptr, X, ldx, W,
-                       ldw, n_vec, alpha, c->J, half_k2, a[0], a[1], a[2], b[0], b[1], b[2]);
+    hipLaunchKernelGGL((mf_apply_kernel<T, NP, KT>), dim3(grid), dim3(MfT<T>::NT), sh, c->stream, tab, qd,
+                       c->cell_nodes.ptr, c->colour_cells.ptr + c->colour_off[k], (int)total, n_chunks,
+                       c->minv_sqrt.ptr, X, ldx, W, ldw, n_vec, alpha, (T)c->J, half_k2, a[0], a[1], a[2], b[0],
+                       b[1], b[2]);
     LAUNCH_CHECK();
   }
 }
 
 template <int NP>
-void launch_mf_np(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
-                  double alpha) {
-  if (kp.gamma) launch_mf_t<NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha);
-  else launch_mf_t<NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+void launch_mf_np(chfsi_ctx* c, const KPoint& kp, bool fp64, const double2* X, int64_t ldx, double2* W, int64_t ldw,
+                  int n_vec, double alpha) {
+  if (fp64) {
+    if (kp.gamma) launch_mf_t<double, NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+    else launch_mf_t<double, NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+  } else {
+    if (kp.gamma) launch_mf_t<float, NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+    else launch_mf_t<float, NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+  }
 }
 
 }  // namespace
@@ -305,32 +349,38 @@ void mf_prepare(chfsi_ctx* c) {
   for (int q = 0; q < n; ++q)
     for (int r = 0; r < n; ++r) tab[n * n + q * n + r] = Dlag[(size_t)r * n + q];
   for (int q = 0; q < n; ++q) tab[2 * n * n + q] = c->ref.wq[q];
+  std::vector<float> tab32(tab.begin(), tab.end());
   c->mf_tab.upload(tab.data(), tab.size(), c->stream);
+  c->mf_tab32.upload(tab32.data(), tab32.size(), c->stream);
+  CHFSI_HIP(hipStreamSynchronize(c->stream));   // the host tables go out of scope
 }
 
 void mf_set_local(chfsi_ctx* c, const double* V, const double* B) {
   if (c->mf_tab.n == 0) mf_prepare(c);
   const int64_t n_points = (int64_t)c->n_cells * c->nq3;
   c->mf_qd.alloc((size_t)n_points * 4);
+  c->mf_qd32.alloc((size_t)n_points * 4);
   DevBuf<double> w1;
   w1.upload(c->ref.wq.data(), c->ref.wq.size(), c->stream);
   hipLaunchKernelGGL(mf_qdata_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 8192)), dim3(256), 0,
-                     c->stream, V, B, w1.ptr, c->J, c->nq, n_points, reinterpret_cast<double4*>(c->mf_qd.ptr));
+                     c->stream, V, B, w1.ptr, c->J, c->nq, n_points, reinterpret_cast<double4*>(c->mf_qd.ptr),
+                     reinterpret_cast<float4*>(c->mf_qd32.ptr));
   LAUNCH_CHECK();
   CHFSI_HIP(hipStreamSynchronize(c->stream));
 }
 
-void launch_mf_products(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-                        int n_vec, double alpha) {
+void launch_mf_products(chfsi_ctx* c, const KPoint& kp, int prec, const double2* X, int64_t ldx, double2* W,
+                        int64_t ldw, int n_vec, double alpha) {
+  const bool fp64 = prec != CHFSI_PREC_MIXED;
   switch (c->np1) {
-    case 2: launch_mf_np<2>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 3: launch_mf_np<3>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 4: launch_mf_np<4>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 5: launch_mf_np<5>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 6: launch_mf_np<6>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 7: launch_mf_np<7>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 8: launch_mf_np<8>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
-    case 9: launch_mf_np<9>(c, kp, X, ldx, W, ldw, n_vec, alpha); break;
+    case 2: launch_mf_np<2>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 3: launch_mf_np<3>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 4: launch_mf_np<4>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 5: launch_mf_np<5>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 6: launch_mf_np<6>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 7: launch_mf_np<7>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 8: launch_mf_np<8>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 9: launch_mf_np<9>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
     default: throw Error{CHFSI_EINVAL, "matrix-free apply: unsupported p"};
   }
 }

@@ -29,31 +29,38 @@ __device__ __forceinline__ int sf_line_base(int l) {
   else return l;                                                        // l = x + NP y
 }
 
+// Complex pair of the arithmetic type.
+template <class T> struct SfC2;
+template <> struct SfC2<double> { typedef double2 type; };
+template <> struct SfC2<float> { typedef float2 type; };
+
 // out = contraction of fields 0..NF-1 along DIM with the n_p x n_p table M:
 //   FWD:  out[.. o ..] = sum_i M[i][o] in[.. i ..]   (nodes -> points with M = B)
 //   !FWD: out[.. o ..] = sum_i M[o][i] in[.. i ..]   (points -> nodes)
 // in and out may be the same buffer: a thread reads its whole line before it
 // writes it, and the lines of one pass are disjoint.
-template <int NP, int NF, int DIM, bool FWD, int NT = 256>
-__device__ __forceinline__ void sf_line_pass(const double* __restrict__ M, const double2* in, double2* out) {
+template <int NP, int NF, int DIM, bool FWD, int NT = 256, class T = double>
+__device__ __forceinline__ void sf_line_pass(const T* __restrict__ M, const typename SfC2<T>::type* in,
+                                             typename SfC2<T>::type* out) {
+  typedef typename SfC2<T>::type C2;
   constexpr int N2 = NP * NP, N3 = N2 * NP;
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
   for (int t = threadIdx.x; t < N2 * NF; t += NT) {
     const int l = t % N2, f = t / N2;
     const int base = f * N3 + sf_line_base<NP, DIM>(l);
-    double2 v[NP];
+    C2 v[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) v[j] = in[base + j * S];
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
-      double re = 0.0, im = 0.0;
+      T re = 0, im = 0;
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
-        const double m = FWD ? M[i * NP + o] : M[o * NP + i];
+        const T m = FWD ? M[i * NP + o] : M[o * NP + i];
         re = fma(m, v[i].x, re);
         im = fma(m, v[i].y, im);
       }
-      out[base + o * S] = double2{re, im};
+      out[base + o * S] = C2{re, im};
     }
   }
 }
