@@ -704,7 +704,7 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
 // columns are one 128-byte line of a row), interpolates along z there, and the y
 // and x passes run in place in LDS; the next chunk's z-lines are loaded while the
 // current chunk runs its LDS phases (LDS-only barriers).  Whole lines per row and
-// chunk keep the block's HBM traffic at one read.  tab = [B: n_p^2][Dq: n_p^2][w: n_p].
+// chunk keep the block's HBM traffic at one read.  tab = the matrix-free tables [B][Dq][w][even-odd tables].
 // Work item bid -> cell bid % n_cells, column group bid / n_cells, neighbouring
 // cells (which share face nodes) on one XCD.
 constexpr int kQfThreads = 512;
@@ -723,8 +723,8 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
   constexpr int QPT = (N3 + NT - 1) / NT;
   extern __shared__ double2 qf_sm[];
   double2* buf = qf_sm;                 // [CW][NS][N3]
-  const double* Bt = tab;
   const double* w1 = tab + 2 * N2;
+  const double* eoBf = tab + 2 * N2 + NP;    // even-odd table of B (sf_eo)
   const int total = n_cells * n_groups;
   const int per_xcd = (total + 7) / 8;
   const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -778,16 +778,10 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
         u[i] = double2{f * zv[k][i].x, f * zv[k][i].y};
       }
       double2* out = buf + (c * NS + s) * N3 + l;
+      double2 r[NP];
+      sf_eo<double, NP, false>(eoBf, u, r);
 #pragma unroll
-      for (int o = 0; o < NP; ++o) {
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          re = fma(Bt[i * NP + o], u[i].x, re);
-          im = fma(Bt[i * NP + o], u[i].y, im);
-        }
-        out[o * N2] = double2{re, im};
-      }
+      for (int o = 0; o < NP; ++o) out[o * N2] = r[o];
     }
     if (n0 + CW < c_end) {
 #pragma unroll
@@ -796,9 +790,9 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
         for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(n0 + CW + tcol[k], c_end - 1)];
     }
     lds_barrier();
-    sf_line_pass<NP, NF, 1, true, NT>(Bt, buf, buf);
+    sf_line_pass<NP, NF, 1, NT>(eoBf, buf, buf);
     lds_barrier();
-    sf_line_pass<NP, NF, 0, true, NT>(Bt, buf, buf);
+    sf_line_pass<NP, NF, 0, NT>(eoBf, buf, buf);
     lds_barrier();
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {

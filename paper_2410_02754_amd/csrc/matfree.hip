@@ -29,6 +29,8 @@
 // one (column, spin) field, keeps it in registers and writes the contracted
 // line, so every LDS value read feeds n_p multiply-adds.  Within a colour no
 // two cells share a node, so the scatter is a plain read-add-write.
+#include <functional>
+
 #include "mfma.h"
 #include "sumfact.h"
 
@@ -55,11 +57,14 @@ constexpr int mf_cw(int NP) { return sizeof(T) == 8 ? sf_cols(NP) : 2 * sf_cols(
 //   G = Dq U,  W += a_d Dq^T (wJ G) - i b_d wJ G,
 // a_d = (2/h_d)^2 / 2, b_d = k_d (2/h_d), wJ = J w_x w_y w_z at each point.
 // BWD: W along the line is then complete (the other directions ran before), so
-// the backward interpolation along DIM (W -> B W, table Bt) is applied in place.
+// the backward interpolation along DIM (W -> B W) is applied in place.
+// eo: even-odd tables of Dq (G = Dq U), Dq^T (the transposed contraction) and
+// B^T (points -> nodes), see sf_eo.
 template <class T, int NP, int CW, int DIM, bool KT, bool BWD>
-__device__ __forceinline__ void grad_pass(const T* __restrict__ Dq, const T* __restrict__ w1, T J, T a_d, T b_d,
+__device__ __forceinline__ void grad_pass(const T* __restrict__ eoDf, const T* __restrict__ eoDb,
+                                          const T* __restrict__ eoBb, const T* __restrict__ w1, T J, T a_d, T b_d,
                                           const typename MfT<T>::C2* __restrict__ U,
-                                          typename MfT<T>::C2* __restrict__ W, const T* __restrict__ Bt) {
+                                          typename MfT<T>::C2* __restrict__ W) {
   typedef typename MfT<T>::C2 C2;
   constexpr int NT = MfT<T>::NT;
   constexpr int N2 = NP * NP, N3 = N2 * NP;
@@ -72,31 +77,20 @@ __device__ __forceinline__ void grad_pass(const T* __restrict__ Dq, const T* __r
     C2 u[NP], g[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) u[j] = U[base + j * S];
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      T re = 0, im = 0;
-#pragma unroll
-      for (int r = 0; r < NP; ++r) {
-        re = fma(Dq[q * NP + r], u[r].x, re);
-        im = fma(Dq[q * NP + r], u[r].y, im);
-      }
-      g[q] = C2{re, im};
-    }
-    C2 fk[NP];
+    sf_eo<T, NP, true>(eoDf, u, g);
+    C2 fk[NP], dw[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const T s = a_d * wl * w1[q];
       fk[q] = C2{s * g[q].x, s * g[q].y};
     }
+    sf_eo<T, NP, true>(eoDb, fk, dw);
     C2 wv[NP];
 #pragma unroll
     for (int r = 0; r < NP; ++r) {
       C2 acc = W[base + r * S];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        acc.x = fma(Dq[q * NP + r], fk[q].x, acc.x);
-        acc.y = fma(Dq[q * NP + r], fk[q].y, acc.y);
-      }
+      acc.x += dw[r].x;
+      acc.y += dw[r].y;
       if constexpr (KT) {
         // -i b wJ g = b wJ g.y - i b wJ g.x
         const T s = b_d * wl * w1[r];
@@ -105,25 +99,20 @@ __device__ __forceinline__ void grad_pass(const T* __restrict__ Dq, const T* __r
       }
       wv[r] = acc;
     }
+    if constexpr (BWD) {
+      C2 o[NP];
+      sf_eo<T, NP, false>(eoBb, wv, o);
 #pragma unroll
-    for (int o = 0; o < NP; ++o) {
-      if constexpr (BWD) {
-        T re = 0, im = 0;
+      for (int r = 0; r < NP; ++r) W[base + r * S] = o[r];
+    } else {
 #pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          re = fma(Bt[o * NP + i], wv[i].x, re);
-          im = fma(Bt[o * NP + i], wv[i].y, im);
-        }
-        W[base + o * S] = C2{re, im};
-      } else {
-        W[base + o * S] = wv[o];
-      }
+      for (int r = 0; r < NP; ++r) W[base + r * S] = wv[r];
     }
   }
 }
 
-// tab: [B: NP*NP][Dq: NP*NP][w: NP], qd: [E][NP^3] of (wJ V, wJ Bx, wJ By, wJ Bz),
-// both in the arithmetic type T.
+// tab: [B: NP*NP][Dq: NP*NP][w: NP][even-odd tables of B, B^T, Dq, Dq^T], qd:
+// [E][NP^3] of (wJ V, wJ Bx, wJ By, wJ Bz), both in the arithmetic type T.
 //
 // One workgroup per work item (cell of the colour, chunk of CW columns); items
 // are cell major and consecutive items run on one XCD (workgroup b on XCD b % 8),
@@ -146,9 +135,11 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
   extern __shared__ double2 mf_sm_raw[];
   C2* bufA = reinterpret_cast<C2*>(mf_sm_raw);   // [CW][2][N3]
   C2* bufB = bufA + CW * 2 * N3;                 // [CW][2][N3]
-  const T* Bt = tab;
-  const T* Dq = tab + N2;
   const T* w1 = tab + 2 * N2;
+  const T* eoBf = tab + 2 * N2 + NP;
+  const T* eoBb = eoBf + sf_eo_size(NP);
+  const T* eoDf = eoBb + sf_eo_size(NP);
+  const T* eoDb = eoDf + sf_eo_size(NP);
   const int tid = threadIdx.x;
 
   const int per_xcd = (total + 7) / 8;
@@ -184,21 +175,15 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
       u[z] = C2{(T)(f * xr[z].x), (T)(f * xr[z].y)};
     }
     C2* out = bufB + (tc * 2 + ts) * N3 + tl;
+    C2 r[NP];
+    sf_eo<T, NP, false>(eoBf, u, r);
 #pragma unroll
-    for (int o = 0; o < NP; ++o) {
-      T re = 0, im = 0;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        re = fma(Bt[i * NP + o], u[i].x, re);
-        im = fma(Bt[i * NP + o], u[i].y, im);
-      }
-      out[o * N2] = C2{re, im};
-    }
+    for (int o = 0; o < NP; ++o) out[o * N2] = r[o];
   }
   lds_barrier();
-  sf_line_pass<NP, 2 * CW, 1, true, NT, T>(Bt, bufB, bufB);   // in place: a thread owns its line
+  sf_line_pass<NP, 2 * CW, 1, NT, T>(eoBf, bufB, bufB);   // in place: a thread owns its line
   lds_barrier();
-  sf_line_pass<NP, 2 * CW, 0, true, NT, T>(Bt, bufB, bufB);   // U in bufB
+  sf_line_pass<NP, 2 * CW, 0, NT, T>(eoBf, bufB, bufB);   // U in bufB
   lds_barrier();
 
   // potential and field terms at the points
@@ -218,33 +203,26 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
     bufA[(c * 2 + 1) * N3 + q] = w2;
   }
   lds_barrier();
-  grad_pass<T, NP, CW, 2, KT, false>(Dq, w1, J, a2, b2, bufB, bufA, Bt);
+  grad_pass<T, NP, CW, 2, KT, false>(eoDf, eoDb, eoBb, w1, J, a2, b2, bufB, bufA);
   lds_barrier();
-  grad_pass<T, NP, CW, 1, KT, false>(Dq, w1, J, a1, b1, bufB, bufA, Bt);
+  grad_pass<T, NP, CW, 1, KT, false>(eoDf, eoDb, eoBb, w1, J, a1, b1, bufB, bufA);
   lds_barrier();
-  grad_pass<T, NP, CW, 0, KT, true>(Dq, w1, J, a0, b0, bufB, bufA, Bt);   // and W -> B W along x
+  grad_pass<T, NP, CW, 0, KT, true>(eoDf, eoDb, eoBb, w1, J, a0, b0, bufB, bufA);   // and W -> B W along x
   lds_barrier();
-  sf_line_pass<NP, 2 * CW, 1, false, NT, T>(Bt, bufA, bufA);
+  sf_line_pass<NP, 2 * CW, 1, NT, T>(eoBb, bufA, bufA);
   lds_barrier();
 
   // last backward contraction along z, then Y[rows] += alpha M^{-1/2} y (the
   // rows' indices, factors and old values loaded together before the stores)
   if (ok) {
     const C2* in = bufA + (tc * 2 + ts) * N3 + tl;
-    C2 v[NP];
+    C2 v[NP], y[NP];
     double2 r[NP];
 #pragma unroll
     for (int z = 0; z < NP; ++z) v[z] = in[z * N2];
+    sf_eo<T, NP, false>(eoBb, v, y);
 #pragma unroll
-    for (int o = 0; o < NP; ++o) {
-      T re = 0, im = 0;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        re = fma(Bt[o * NP + i], v[i].x, re);
-        im = fma(Bt[o * NP + i], v[i].y, im);
-      }
-      r[o] = double2{(double)re, (double)im};
-    }
+    for (int o = 0; o < NP; ++o) r[o] = double2{(double)y[o].x, (double)y[o].y};
     int64_t I[NP];
 #pragma unroll
     for (int o = 0; o < NP; ++o) I[o] = nodes[tl + o * N2];
@@ -349,6 +327,36 @@ void mf_prepare(chfsi_ctx* c) {
   for (int q = 0; q < n; ++q)
     for (int r = 0; r < n; ++r) tab[n * n + q * n + r] = Dlag[(size_t)r * n + q];
   for (int q = 0; q < n; ++q) tab[2 * n * n + q] = c->ref.wq[q];
+  // even-odd tables of B (nodes -> points), B^T, Dq (G = Dq U) and Dq^T, each as
+  // out[o] = sum_i M[i][o] in[i]
+  const int h = n / 2, es = 2 * h * h + 2 * h + 1;
+  auto Bm = [&](int i, int o) { return tab[i * n + o]; };
+  auto Dm = [&](int q, int r) { return tab[n * n + q * n + r]; };
+  auto eo = [&](const std::function<double(int, int)>& M, bool skew) {
+    double big = 0.0, dev = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int o = 0; o < n; ++o) {
+        big = std::max(big, std::fabs(M(i, o)));
+        dev = std::max(dev, std::fabs(M(n - 1 - i, n - 1 - o) - (skew ? -1.0 : 1.0) * M(i, o)));
+      }
+    CHFSI_CHECK(dev <= 1e-12 * std::max(1.0, big), CHFSI_EINVAL, "quadrature rule is not symmetric");
+    std::vector<double> t(es, 0.0);
+    for (int i = 0; i < h; ++i)
+      for (int o = 0; o < h; ++o) {
+        t[i * h + o] = 0.5 * (M(i, o) + M(i, n - 1 - o));
+        t[h * h + i * h + o] = 0.5 * (M(i, o) - M(i, n - 1 - o));
+      }
+    if (n % 2) {
+      for (int o = 0; o < h; ++o) t[2 * h * h + o] = M(h, o);
+      for (int i = 0; i < h; ++i) t[2 * h * h + h + i] = M(i, h);
+      t[2 * h * h + 2 * h] = M(h, h);
+    }
+    tab.insert(tab.end(), t.begin(), t.end());
+  };
+  eo([&](int i, int o) { return Bm(i, o); }, false);
+  eo([&](int i, int o) { return Bm(o, i); }, false);
+  eo([&](int i, int o) { return Dm(o, i); }, true);
+  eo([&](int i, int o) { return Dm(i, o); }, true);
   std::vector<float> tab32(tab.begin(), tab.end());
   c->mf_tab.upload(tab.data(), tab.size(), c->stream);
   c->mf_tab32.upload(tab32.data(), tab32.size(), c->stream);
