@@ -577,16 +577,9 @@ def bench_batch(args, torch):
     return out
 
 
-def bench_adjoint(args, torch):
-    """The differentiation workload: 10^3 cells, p=5 (250k spinor dofs), N=256,
-    degree 16; forward filter and its adjoint (checkpoints every 4 steps) giving
-    dL/dX, dL/dV_eff and dL/dB_xc at the quadrature points."""
-    import synth
-    s = synth.config("adjoint")
-    op = build_operator(s, torch)
-    pts = op.quad_points().reshape(-1, 3)
-    V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
-    B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+def _adjoint_run(args, s, op, torch):
+    """Median forward and backward times of the degree-m filter and its adjoint on
+    op, the adjoint identity of the last run, and its outputs (Xbar, dV, dB)."""
     X = torch.empty((s.n_dof, s.n_vec), dtype=torch.complex128, device="cuda")
     op.fill_random(X, s.seed, n_total_cols=s.n_vec)
     v0 = torch.empty((s.n_dof, 1), dtype=torch.complex128, device="cuda")
@@ -597,7 +590,8 @@ def bench_adjoint(args, torch):
     G = torch.empty_like(X)
     op.fill_random(G, s.seed + 2, n_total_cols=s.n_vec)
     Y, W, Xb = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
-    dV, dB = torch.zeros_like(V), torch.zeros_like(B)
+    dV = torch.zeros((op.n_cells, op.nq3), dtype=torch.float64, device="cuda")
+    dB = torch.zeros((op.n_cells, op.nq3, 3), dtype=torch.float64, device="cuda")
     tf, tb = [], []
     for it in range(args.warmup + args.steps):
         Y.copy_(X)
@@ -618,11 +612,22 @@ def bench_adjoint(args, torch):
     lhs = torch.vdot(G.flatten(), Y.flatten())
     rhs = torch.vdot(Xb.flatten(), X.flatten())
     rel = float((lhs - rhs).abs() / lhs.abs())
-    ws = op.filter_backward_workspace(s.n_vec, s.degree, 4) if hasattr(op, "filter_backward_workspace") else None
+    ws = op.filter_backward_workspace(s.n_vec, s.degree, 4)
+    return float(np.median(tf)), float(np.median(tb)), rel, flops, ws, (Xb, dV, dB)
+
+
+def bench_adjoint(args, torch):
+    """The differentiation workload: 10^3 cells, p=5 (250k spinor dofs), N=256,
+    degree 16; forward filter and its adjoint (checkpoints every 4 steps) giving
+    dL/dX, dL/dV_eff and dL/dB_xc at the quadrature points, with the stored cell
+    matrices and with the matrix-free operator."""
+    import synth
+    s = synth.config("adjoint")
+    op = build_operator(s, torch)
+    tfm, tbm, rel, flops, ws, outs = _adjoint_run(args, s, op, torch)
     op.close()
-    tfm, tbm = float(np.median(tf)), float(np.median(tb))
     log(f"[bench] adjoint: forward {1e3 * tfm:.1f} ms, backward {1e3 * tbm:.1f} ms, identity rel {rel:.1e}")
-    return {
+    out = {
         "metric": "Chebyshev filter adjoint: dL/dX, dL/dV_eff, dL/dB_xc (checkpoints every 4 steps)",
         "value": round(1e3 * tbm, 2), "unit": "ms per backward", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * (tfm + tbm), 2), "higher_is_better": False,
@@ -633,6 +638,17 @@ def bench_adjoint(args, torch):
         "backward_over_forward": round(tbm / tfm, 3), "adjoint_identity_rel": rel,
         "workspace": ws,
     }
+    if not args.no_matfree and s.n_q == s.p + 1:
+        opm = build_operator(s, torch, form="matrix_free")
+        tfm2, tbm2, rel2, _, _, outs2 = _adjoint_run(args, s, opm, torch)
+        opm.close()
+        diffs = [float((u - v).abs().max() / v.abs().max()) for u, v in zip(outs2, outs)]
+        out["matrix_free"] = {"forward_ms": round(1e3 * tfm2, 2), "backward_ms": round(1e3 * tbm2, 2),
+                              "adjoint_identity_rel": rel2,
+                              "max_rel_diff_vs_cell_form": {"Xbar": diffs[0], "dV": diffs[1], "dB": diffs[2]}}
+        log(f"[bench] adjoint matrix-free: forward {1e3 * tfm2:.1f} ms, backward {1e3 * tbm2:.1f} ms, "
+            f"rel diff vs cell form {max(diffs):.1e}")
+    return out
 
 
 if __name__ == "__main__":

@@ -12,9 +12,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _setup(s):
+def _setup(s, form="cell"):
     from paper_2410_02754_amd import Operator
-    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts)
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts, form=form)
     pts = op.quad_points().reshape(-1, 3)
     V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
     B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
@@ -27,11 +27,12 @@ SMALL = lambda: synth.make_system("adjs", n_cells=(2, 3, 2), box=(4.0, 5.0, 4.0)
                                   kpts=[(0.1, -0.15, 0.05)], n_atoms=2, lmax=1, rcut_sigmas=5.0, n_vec=5)
 
 
-def test_apply_backward_matches_oracle_and_closed_form():
+@pytest.mark.parametrize("form", ["cell", "matrix_free"])
+def test_apply_backward_matches_oracle_and_closed_form(form):
     from paper_2410_02754_amd.autograd import apply_h
     s = SMALL()
     mesh, H, MD, Vo, Bo = ham.build(s, synth.veff, synth.bxc)
-    op, V, B = _setup(s)
+    op, V, B = _setup(s, form)
     X0 = synth.random_block(3, s.n_dof, s.n_vec)
     X = torch.tensor(X0, device="cuda", requires_grad=True)
     Vr = V.clone().requires_grad_(True)
@@ -51,10 +52,11 @@ def test_apply_backward_matches_oracle_and_closed_form():
     op.close()
 
 
-def test_filter_backward_matches_oracle():
+@pytest.mark.parametrize("form", ["cell", "matrix_free"])
+def test_filter_backward_matches_oracle(form):
     s = SMALL()
     mesh, H, MD, Vo, Bo = ham.build(s, synth.veff, synth.bxc)
-    op, V, B = _setup(s)
+    op, V, B = _setup(s, form)
     lam = np.linalg.eigvalsh(H.toarray())
     m, a, b, a0 = 7, float(lam[30]), float(lam[-1] + 1.0), float(lam[0])
     X0 = synth.random_block(4, s.n_dof, s.n_vec)
