@@ -199,6 +199,7 @@ struct chfsi_ctx {
   chfsi::DevBuf<double> mf_tab;               // [B: np1^2][Dq: np1^2][w: np1]
   chfsi::DevBuf<double> mf_qd;                // [E][nq^3][4]: w_q J (V, Bx, By, Bz)
   chfsi::DevBuf<float> mf_tab32, mf_qd32;     // FP32 copies for mixed precision
+  chfsi::DevBuf<float> mf_kin32;              // [3][nq^3] FP32 kinetic weights per point
   // stage timing
   bool stats_on = false;
   std::vector<chfsi::StageRec> pending;

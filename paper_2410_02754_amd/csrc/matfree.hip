@@ -60,10 +60,13 @@ constexpr int mf_cw(int NP) { return sizeof(T) == 8 ? sf_cols(NP) : 2 * sf_cols(
 // the backward interpolation along DIM (W -> B W) is applied in place.
 // eo: even-odd tables of Dq (G = Dq U), Dq^T (the transposed contraction) and
 // B^T (points -> nodes), see sf_eo.
+// In FP32 the kinetic weights a_d wJ come per point from kin (formed in FP64 and
+// rounded once): products of the shared 1-D weights rounded in FP32 would bias
+// the operator the same way in every cell.
 template <class T, int NP, int CW, int DIM, bool KT, bool BWD>
 __device__ __forceinline__ void grad_pass(const T* __restrict__ eoDf, const T* __restrict__ eoDb,
                                           const T* __restrict__ eoBb, const T* __restrict__ w1, T J, T a_d, T b_d,
-                                          const typename MfT<T>::C2* __restrict__ U,
+                                          const T* __restrict__ kin, const typename MfT<T>::C2* __restrict__ U,
                                           typename MfT<T>::C2* __restrict__ W) {
   typedef typename MfT<T>::C2 C2;
   constexpr int NT = MfT<T>::NT;
@@ -71,19 +74,20 @@ __device__ __forceinline__ void grad_pass(const T* __restrict__ eoDf, const T* _
   constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
   for (int t = threadIdx.x; t < N2 * 2 * CW; t += NT) {
     const int l = t % N2, f = t / N2;
-    const int base = f * N3 + sf_line_base<NP, DIM>(l);
+    const int lb = sf_line_base<NP, DIM>(l);
+    const int base = f * N3 + lb;
     // the two coordinates held fixed along the line are l % NP and l / NP
     const T wl = J * w1[l % NP] * w1[l / NP];
+    T kw[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) kw[q] = (sizeof(T) == 4) ? kin[lb + q * S] : a_d * wl * w1[q];
     C2 u[NP], g[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) u[j] = U[base + j * S];
     sf_eo<T, NP, true>(eoDf, u, g);
     C2 fk[NP], dw[NP];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const T s = a_d * wl * w1[q];
-      fk[q] = C2{s * g[q].x, s * g[q].y};
-    }
+    for (int q = 0; q < NP; ++q) fk[q] = C2{kw[q] * g[q].x, kw[q] * g[q].y};
     sf_eo<T, NP, true>(eoDb, fk, dw);
     C2 wv[NP];
 #pragma unroll
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
     const T* __restrict__ tab, const typename MfT<T>::Q4* __restrict__ qd, const int32_t* __restrict__ cell_nodes,
     const int32_t* __restrict__ cells, int total, int n_chunks, const double* __restrict__ minv_sqrt,
     const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y, int64_t ldy, int n_vec, double alpha,
-    T J, T half_k2, T a0, T a1, T a2, T b0, T b1, T b2) {
+    T J, T half_k2, T a0, T a1, T a2, T b0, T b1, T b2, const T* __restrict__ kin) {
   typedef typename MfT<T>::C2 C2;
   typedef typename MfT<T>::Q4 Q4;
   constexpr int NT = MfT<T>::NT;
@@ -203,11 +207,11 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
     bufA[(c * 2 + 1) * N3 + q] = w2;
   }
   lds_barrier();
-  grad_pass<T, NP, CW, 2, KT, false>(eoDf, eoDb, eoBb, w1, J, a2, b2, bufB, bufA);
+  grad_pass<T, NP, CW, 2, KT, false>(eoDf, eoDb, eoBb, w1, J, a2, b2, kin + 2 * N3, bufB, bufA);
   lds_barrier();
-  grad_pass<T, NP, CW, 1, KT, false>(eoDf, eoDb, eoBb, w1, J, a1, b1, bufB, bufA);
+  grad_pass<T, NP, CW, 1, KT, false>(eoDf, eoDb, eoBb, w1, J, a1, b1, kin + 1 * N3, bufB, bufA);
   lds_barrier();
-  grad_pass<T, NP, CW, 0, KT, true>(eoDf, eoDb, eoBb, w1, J, a0, b0, bufB, bufA);   // and W -> B W along x
+  grad_pass<T, NP, CW, 0, KT, true>(eoDf, eoDb, eoBb, w1, J, a0, b0, kin + 0 * N3, bufB, bufA);   // and W -> B W along x
   lds_barrier();
   sf_line_pass<NP, 2 * CW, 1, NT, T>(eoBb, bufA, bufA);
   lds_barrier();
@@ -271,12 +275,15 @@ void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, 
   const T half_k2 = (T)(0.5 * (kp.k[0] * kp.k[0] + kp.k[1] * kp.k[1] + kp.k[2] * kp.k[2]));
   const T* tab = nullptr;
   const Q4* qd = nullptr;
+  const T* kin = nullptr;    // FP32 only (FP64 forms the weights in the kernel)
   if constexpr (sizeof(T) == 8) {
     tab = c->mf_tab.ptr;
     qd = reinterpret_cast<const Q4*>(c->mf_qd.ptr);
+    kin = tab;
   } else {
     tab = c->mf_tab32.ptr;
     qd = reinterpret_cast<const Q4*>(c->mf_qd32.ptr);
+    kin = c->mf_kin32.ptr;
   }
   const double np3 = (double)NP * NP * NP;
   for (int k = 0; k < c->n_colours; ++k) {
@@ -295,7 +302,7 @@ void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, 
     hipLaunchKernelGGL((mf_apply_kernel<T, NP, KT>), dim3(grid), dim3(MfT<T>::NT), sh, c->stream, tab, qd,
                        c->cell_nodes.ptr, c->colour_cells.ptr + c->colour_off[k], (int)total, n_chunks,
                        c->minv_sqrt.ptr, X, ldx, W, ldw, n_vec, alpha, (T)c->J, half_k2, a[0], a[1], a[2], b[0],
-                       b[1], b[2]);
+                       b[1], b[2], kin);
     LAUNCH_CHECK();
   }
 }
@@ -358,8 +365,18 @@ void mf_prepare(chfsi_ctx* c) {
   eo([&](int i, int o) { return Dm(o, i); }, true);
   eo([&](int i, int o) { return Dm(i, o); }, true);
   std::vector<float> tab32(tab.begin(), tab.end());
+  // FP32 kinetic weights per point and direction: (2/h_d)^2 / 2 * J w_x w_y w_z
+  const int n3 = n * n * n;
+  std::vector<float> kin32(3 * (size_t)n3);
+  for (int d = 0; d < 3; ++d) {
+    const double sd = 2.0 / c->h[d];
+    for (int q = 0; q < n3; ++q)
+      kin32[(size_t)d * n3 + q] =
+          (float)(0.5 * sd * sd * c->J * c->ref.wq[q % n] * c->ref.wq[(q / n) % n] * c->ref.wq[q / (n * n)]);
+  }
   c->mf_tab.upload(tab.data(), tab.size(), c->stream);
   c->mf_tab32.upload(tab32.data(), tab32.size(), c->stream);
+  c->mf_kin32.upload(kin32.data(), kin32.size(), c->stream);
   CHFSI_HIP(hipStreamSynchronize(c->stream));   // the host tables go out of scope
 }
 
