@@ -365,6 +365,66 @@ void mf_prepare(chfsi_ctx* c) {
   eo([&](int i, int o) { return Dm(o, i); }, true);
   eo([&](int i, int o) { return Dm(i, o); }, true);
   std::vector<float> tab32(tab.begin(), tab.end());
+  // The FP32 tables keep identities of the exact ones, so that rounding them does
+  // not perturb every cell the same way: the interpolation reproduces constants
+  // and linear functions (sum_a l_a = 1, sum_a xi_a l_a(x) = x) and the
+  // collocation derivative maps them to 0 and 1.  In each sum the closing entry
+  // is re-formed in FP64 from the rounded others.  The tables of the transposed
+  // contractions are then taken from the rounded forward ones (for a
+  // centrosymmetric M the even-odd blocks of M^T are those of M transposed; for a
+  // skew one the two blocks also swap), so that the FP32 operator keeps the exact
+  // adjoint structure of the FP64 one.
+  {
+    const int b0 = 2 * n * n + n, bb0 = b0 + es, d0 = b0 + 2 * es, db0 = b0 + 3 * es;
+    const std::vector<double>& xi = c->ref.xi;   // GLL nodes (input of B)
+    const std::vector<double>& xq = c->ref.xq;   // quadrature points (output of B, input of Dq)
+    auto Af = [&](int t0, int i, int o) -> float& { return tab32[t0 + i * h + o]; };
+    auto Cf = [&](int t0, int i, int o) -> float& { return tab32[t0 + h * h + i * h + o]; };
+    for (int o = 0; o < h; ++o) {
+      // B: constants (sum of the A column and the middle row) and linear functions (C column)
+      double sa = 0.0, sc = 0.0, da = 0.0, dc = 0.0;
+      for (int i = 0; i < h; ++i) {
+        if (!(n % 2 == 0 && i == h - 1)) sa += Af(b0, i, o);
+        if (i > 0) sc += Cf(b0, i, o) * xi[i];
+        if (i > 0) da += Af(d0, i, o) * xq[i];
+        if (!(n % 2 == 0 && i == h - 1)) dc += Cf(d0, i, o);
+      }
+      if (n % 2) {
+        tab32[b0 + 2 * h * h + o] = (float)(1.0 - 2.0 * sa);
+        tab32[d0 + 2 * h * h + o] = (float)(-2.0 * dc);
+      } else {
+        Af(b0, h - 1, o) = (float)(0.5 - sa);
+        Cf(d0, h - 1, o) = (float)(-dc);
+      }
+      Cf(b0, 0, o) = (float)((0.5 * xq[o] - sc) / xi[0]);
+      Af(d0, 0, o) = (float)((0.5 - da) / xq[0]);
+    }
+    if (n % 2) {
+      double sm = 0.0, dm = 0.0;
+      for (int i = 0; i < h; ++i) sm += tab32[b0 + 2 * h * h + h + i];
+      tab32[b0 + 2 * h * h + 2 * h] = (float)(1.0 - 2.0 * sm);
+      for (int i = 1; i < h; ++i) dm += tab32[d0 + 2 * h * h + h + i] * xq[i];
+      tab32[d0 + 2 * h * h + h] = (float)((0.5 - dm) / xq[0]);
+      tab32[d0 + 2 * h * h + 2 * h] = 0.0f;
+    }
+    for (int i = 0; i < h; ++i)
+      for (int o = 0; o < h; ++o) {
+        Af(bb0, i, o) = Af(b0, o, i);
+        Cf(bb0, i, o) = Cf(b0, o, i);
+        Af(db0, i, o) = Cf(d0, o, i);
+        Cf(db0, i, o) = Af(d0, o, i);
+      }
+    if (n % 2) {
+      for (int k = 0; k < h; ++k) {
+        tab32[bb0 + 2 * h * h + k] = tab32[b0 + 2 * h * h + h + k];
+        tab32[bb0 + 2 * h * h + h + k] = tab32[b0 + 2 * h * h + k];
+        tab32[db0 + 2 * h * h + k] = tab32[d0 + 2 * h * h + h + k];
+        tab32[db0 + 2 * h * h + h + k] = tab32[d0 + 2 * h * h + k];
+      }
+      tab32[bb0 + 2 * h * h + 2 * h] = tab32[b0 + 2 * h * h + 2 * h];
+      tab32[db0 + 2 * h * h + 2 * h] = 0.0f;
+    }
+  }
   // FP32 kinetic weights per point and direction: (2/h_d)^2 / 2 * J w_x w_y w_z
   const int n3 = n * n * n;
   std::vector<float> kin32(3 * (size_t)n3);
