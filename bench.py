@@ -265,7 +265,7 @@ def bench_density(op, s, X, theta, torch, reps=3):
     return res
 
 
-def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch):
+def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch, tables=None):
     """The same FP64 passes (same start block, bound and steps) with the
     matrix-free local operator instead of the stored cell matrices."""
     t = time.perf_counter()
@@ -292,6 +292,8 @@ def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch):
         torch.cuda.synchronize()
         mtotal = time.perf_counter() - t1
         dthm = np.abs(thm - theta_ref)
+        if tables is not None:
+            tables["matrix_free mixed_resid"] = (thm, dthm)
         mixed = {"form": "residual form, FP32 matrix-free and projector products on the correction",
                  "s_per_pass": round(mtotal / args.steps, 3),
                  "filter_s_per_pass": round(sum(mft) / args.steps, 3),
@@ -313,9 +315,11 @@ def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch):
            "setup_s": round(t_setup, 2),
            "kernel": "mf_apply_kernel<7, false> (gather, 12 line contractions per spin, scatter-add)",
            "mean_launch_ms": round(ms, 4),
-           "executed_flops_per_launch": exec_per,
-           "executed_fp64_tflops": round(exec_per / (ms * 1e-3) / 1e12, 3) if ms > 0 else None,
-           "executed_frac_of_78.6": round(exec_per / (ms * 1e-3) / 1e12 / PEAK_FP64, 4) if ms > 0 else None,
+           # 12 dense 1-D contractions per spin (96 n_p^4 per cell and column); the even-odd
+           # form issues about half of these multiply-adds
+           "sumfact_flops_per_launch": exec_per,
+           "sumfact_fp64_tflops": round(exec_per / (ms * 1e-3) / 1e12, 3) if ms > 0 else None,
+           "sumfact_frac_of_78.6": round(exec_per / (ms * 1e-3) / 1e12 / PEAK_FP64, 4) if ms > 0 else None,
            "cell_form_flops_per_launch": fst["cell_flops"] / n_l,
            "max_dtheta_vs_cell_fp64_Ha": float(dth.max()), "max_resid": float(np.max(r)),
            "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in fst["stage_ms"].items() if v > 0}}
@@ -434,7 +438,7 @@ def bench_scale(args, torch):
             log(f"[bench] {key}: max |dtheta| vs fp64 = {dth.max():.3e} Ha")
     op.close()
     if not args.no_matfree and s.n_q == s.p + 1:
-        out["matrix_free"] = bench_matfree(args, s, X, W, Wf, b, theta64, torch)
+        out["matrix_free"] = bench_matfree(args, s, X, W, Wf, b, theta64, torch, tables)
     del X, W, Wf
     if args.eig_table and tables:
         with open(args.eig_table, "w") as fh:

@@ -291,8 +291,9 @@ void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, 
     if (n_in == 0) continue;
     const int64_t total = (int64_t)n_in * n_chunks;
     CHFSI_CHECK(total < (int64_t)1 << 30, CHFSI_EINVAL, "matrix-free apply: too many work items");
-    // algorithmic flops of the dense cell product (the filter's count), executed
-    // flops of the 12 line contractions per spin, and the rows moved
+    // algorithmic flops of the dense cell product (the filter's count), flops of
+    // 12 dense line contractions per spin (the even-odd form issues about half of
+    // those multiply-adds), and the rows moved
     const double n2 = 2.0 * c->nloc;
     const double flops = 8.0 * n2 * n2 * n_vec * n_in;
     const double exec = 96.0 * np3 * NP * (double)n_vec * n_in;
