@@ -137,8 +137,8 @@ enum chfsi_form { CHFSI_FORM_CELL_MATRIX = 0, CHFSI_FORM_MATRIX_FREE = 1 };
  * so the result equals the cell-matrix product up to rounding.  Needs
  * n_q = p + 1 (GL with n_q = p + 1, or GLL).  CHFSI_PREC_MIXED runs the same
  * contractions in FP32 (tables, quadrature data and fields in FP32, rows
- * converted on gather and added into the FP64 output).  chfsi_batch_create
- * rejects contexts of this form.  The call clears the local operator (CHFSI_ESTATE until
+ * converted on gather and added into the FP64 output).  In a batch (below),
+ * tasks of this form run their own per-colour launches.  The call clears the local operator (CHFSI_ESTATE until
  * the next chfsi_set_local builds it in the chosen form).  CHFSI_EINVAL for an
  * unknown form or unsupported mesh. */
 int chfsi_set_apply_form(chfsi_ctx* ctx, int form);
@@ -310,8 +310,10 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
  * a0 < a < b): the same scaled recurrence as chfsi_cheb_filter.  Asynchronous. */
 int chfsi_batch_filter(chfsi_batch* batch, const double* a, const double* b, const double* a0);
 
-/* Chosen column tile width per task (cols_out[n_tasks]) and, if tune_ms is not
- * NULL, the timed cell-stage milliseconds for widths 32, 64, 128 (-1 = not run). */
+/* Chosen column tile width per task (cols_out[n_tasks]; 0 for a task whose
+ * context uses the matrix-free form, which runs its own per-colour launches) and,
+ * if tune_ms is not NULL, the timed cell-stage milliseconds for widths 32, 64,
+ * 128 (-1 = not run). */
 int chfsi_batch_tiles(const chfsi_batch* batch, int* cols_out, double* tune_ms);
 
 /* Free the batch (not the contexts or buffers).  batch may be NULL. */

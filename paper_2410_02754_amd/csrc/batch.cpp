@@ -137,6 +137,15 @@ static void run_filter(chfsi_batch* b, const std::vector<double>& bounds) {
                           g->n_items[col], b->alpha_tab.ptr + (size_t)(k - 1) * nt + g->chunk * kBatchLaunchTasks,
                           src, g->grid[prec == CHFSI_PREC_FP64]);
       }
+    // matrix-free tasks: their own colour launches, alpha read from the table
+    for (int t = 0; t < nt; ++t) {
+      if (b->cb[t] != 0) continue;
+      const auto& tk = b->tasks[t];
+      double2* buf[2] = {(double2*)tk.X_d, (double2*)tk.work_d};
+      const int64_t ld[2] = {tk.ldx, tk.ldw};
+      launch_mf_products(tk.ctx, *b->kps[t], prec, buf[src], ld[src], buf[src ^ 1], ld[src ^ 1], tk.n_vec, 0.0,
+                         b->alpha_tab.ptr + (size_t)(k - 1) * nt + t);
+    }
   }
   if (m & 1)
     for (int t = 0; t < nt; ++t) {
@@ -187,8 +196,6 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
       const auto& tk = tasks[t];
       CHFSI_CHECK(tk.ctx != nullptr, CHFSI_EINVAL, "task without a context");
       CHFSI_CHECK(tk.ctx->have_local, CHFSI_ESTATE, "chfsi_set_local has not been called for a task");
-      CHFSI_CHECK(tk.ctx->form == CHFSI_FORM_CELL_MATRIX, CHFSI_EINVAL,
-                  "batched filtering needs the cell-matrix form");
       CHFSI_CHECK(tk.ctx->stream == b->stream, CHFSI_EINVAL, "all tasks must share one stream");
       CHFSI_CHECK(tk.ik >= 0 && tk.ik < (int)tk.ctx->kp.size(), CHFSI_EINVAL, "k-point index out of range");
       CHFSI_CHECK(tk.X_d && tk.work_d && tk.X_d != tk.work_d && tk.n_vec >= 1 && tk.ldx >= tk.n_vec &&
@@ -206,6 +213,10 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
     const int tprec = prec_mode == CHFSI_PREC_MIXED ? CHFSI_PREC_MIXED : CHFSI_PREC_FP64;
     for (int t = 0; t < n_tasks; ++t) {
       const auto& tk = tasks[t];
+      if (tk.ctx->form == CHFSI_FORM_MATRIX_FREE) {
+        b->cb[t] = 0;   // its own per-task launches, outside the persistent groups
+        continue;
+      }
       const int widest = tk.n_vec > 64 ? 4 : tk.n_vec > 32 ? 2 : 1;
       b->cb[t] = widest;
       if (!(flags & CHFSI_BATCH_AUTOTUNE)) continue;
@@ -225,6 +236,7 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
     }
     std::map<std::tuple<int, int, bool>, int> gid;
     for (int t = 0; t < n_tasks; ++t) {
+      if (b->cb[t] == 0) continue;
       auto key = std::make_tuple(t / kBatchLaunchTasks, b->cb[t], !b->kps[t]->gamma);
       if (!gid.count(key)) {
         gid[key] = (int)b->groups.size();

@@ -262,8 +262,10 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
 bool mf_supported(const chfsi_ctx* c);
 void mf_prepare(chfsi_ctx* c);
 void mf_set_local(chfsi_ctx* c, const double* V, const double* B);
+// W += alpha H_loc X with the matrix-free operator; alpha_d (device, or NULL)
+// overrides alpha at run time (graph replays with new filter bounds)
 void launch_mf_products(chfsi_ctx* c, const KPoint& kp, int prec, const double2* X, int64_t ldx, double2* W,
-                        int64_t ldw, int n_vec, double alpha);
+                        int64_t ldw, int n_vec, double alpha, const double* alpha_d = nullptr);
 void densities(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* occ_d, double* rho,
                double* mag);
 void launch_axpby_rows(chfsi_ctx* c, double2* W, int64_t ldw, const double2* X, int64_t ldx,

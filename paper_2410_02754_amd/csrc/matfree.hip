@@ -129,7 +129,8 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
     const T* __restrict__ tab, const typename MfT<T>::Q4* __restrict__ qd, const int32_t* __restrict__ cell_nodes,
     const int32_t* __restrict__ cells, int total, int n_chunks, const double* __restrict__ minv_sqrt,
     const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y, int64_t ldy, int n_vec, double alpha,
-    T J, T half_k2, T a0, T a1, T a2, T b0, T b1, T b2, const T* __restrict__ kin) {
+    T J, T half_k2, T a0, T a1, T a2, T b0, T b1, T b2, const T* __restrict__ kin,
+    const double* __restrict__ alpha_d) {
   typedef typename MfT<T>::C2 C2;
   typedef typename MfT<T>::Q4 Q4;
   constexpr int NT = MfT<T>::NT;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(MfT<T>::NT) void mf_apply_kernel(
     double2 yo[NP];
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
-      sc[o] = alpha * minv_sqrt[I[o]];
+      sc[o] = (alpha_d ? *alpha_d : alpha) * minv_sqrt[I[o]];
       yo[o] = Y[(2 * I[o] + ts) * ldy + col];
     }
 #pragma unroll
@@ -260,7 +261,7 @@ __global__ void mf_qdata_kernel(const double* __restrict__ V, const double* __re
 
 template <class T, int NP, bool KT>
 void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw, int n_vec,
-                 double alpha) {
+                 double alpha, const double* alpha_d) {
   typedef typename MfT<T>::C2 C2;
   typedef typename MfT<T>::Q4 Q4;
   constexpr int CW = mf_cw<T>(NP);
@@ -303,20 +304,20 @@ void launch_mf_t(chfsi_ctx* c, const KPoint& kp, const double2* X, int64_t ldx, 
     hipLaunchKernelGGL((mf_apply_kernel<T, NP, KT>), dim3(grid), dim3(MfT<T>::NT), sh, c->stream, tab, qd,
                        c->cell_nodes.ptr, c->colour_cells.ptr + c->colour_off[k], (int)total, n_chunks,
                        c->minv_sqrt.ptr, X, ldx, W, ldw, n_vec, alpha, (T)c->J, half_k2, a[0], a[1], a[2], b[0],
-                       b[1], b[2], kin);
+                       b[1], b[2], kin, alpha_d);
     LAUNCH_CHECK();
   }
 }
 
 template <int NP>
 void launch_mf_np(chfsi_ctx* c, const KPoint& kp, bool fp64, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-                  int n_vec, double alpha) {
+                  int n_vec, double alpha, const double* alpha_d) {
   if (fp64) {
-    if (kp.gamma) launch_mf_t<double, NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha);
-    else launch_mf_t<double, NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+    if (kp.gamma) launch_mf_t<double, NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha, alpha_d);
+    else launch_mf_t<double, NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha, alpha_d);
   } else {
-    if (kp.gamma) launch_mf_t<float, NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha);
-    else launch_mf_t<float, NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha);
+    if (kp.gamma) launch_mf_t<float, NP, false>(c, kp, X, ldx, W, ldw, n_vec, alpha, alpha_d);
+    else launch_mf_t<float, NP, true>(c, kp, X, ldx, W, ldw, n_vec, alpha, alpha_d);
   }
 }
 
@@ -456,17 +457,17 @@ void mf_set_local(chfsi_ctx* c, const double* V, const double* B) {
 }
 
 void launch_mf_products(chfsi_ctx* c, const KPoint& kp, int prec, const double2* X, int64_t ldx, double2* W,
-                        int64_t ldw, int n_vec, double alpha) {
+                        int64_t ldw, int n_vec, double alpha, const double* alpha_d) {
   const bool fp64 = prec != CHFSI_PREC_MIXED;
   switch (c->np1) {
-    case 2: launch_mf_np<2>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 3: launch_mf_np<3>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 4: launch_mf_np<4>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 5: launch_mf_np<5>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 6: launch_mf_np<6>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 7: launch_mf_np<7>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 8: launch_mf_np<8>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
-    case 9: launch_mf_np<9>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha); break;
+    case 2: launch_mf_np<2>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 3: launch_mf_np<3>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 4: launch_mf_np<4>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 5: launch_mf_np<5>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 6: launch_mf_np<6>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 7: launch_mf_np<7>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 8: launch_mf_np<8>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
+    case 9: launch_mf_np<9>(c, kp, fp64, X, ldx, W, ldw, n_vec, alpha, alpha_d); break;
     default: throw Error{CHFSI_EINVAL, "matrix-free apply: unsupported p"};
   }
 }

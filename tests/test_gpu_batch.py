@@ -12,9 +12,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _op(s, stream):
+def _op(s, stream, form="cell"):
     from paper_2410_02754_amd import Operator
-    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts, stream=stream.cuda_stream)
+    op = Operator(s.n_cells, s.box, s.p, s.quad, s.n_q, s.kpts, stream=stream.cuda_stream, form=form)
     pts = op.quad_points().reshape(-1, 3)
     V = torch.tensor(synth.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
     B = torch.tensor(synth.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
@@ -34,13 +34,16 @@ def _systems(bmag=0.1):
     return kg, others
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_equals_per_task_bitwise(prec):
+@pytest.mark.parametrize("prec,mf", [("fp64", False), ("mixed", False), ("fp64", True), ("mixed", True)])
+def test_batch_equals_per_task_bitwise(prec, mf):
+    """mf: the second uneven system uses the matrix-free form (its own launches
+    inside the batched, graph-captured filter)."""
     from paper_2410_02754_amd import Batch
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         kg, others = _systems()
-        ops = [_op(kg, stream)] + [_op(s, stream) for s in others]
+        ops = [_op(kg, stream)] + [_op(s, stream, "matrix_free" if (mf and j == 1) else "cell")
+                                   for j, s in enumerate(others)]
         tasks, blocks = [], []
         for ik in range(8):
             X = torch.tensor(synth.random_block(10 + ik, kg.n_dof, kg.n_vec), device="cuda")

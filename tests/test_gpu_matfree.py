@@ -187,14 +187,12 @@ def test_matfree_mixed_residual_filter():
 
 
 def test_matfree_argument_checks():
-    from paper_2410_02754_amd import Batch, ChfsiError, Operator
+    from paper_2410_02754_amd import ChfsiError, Operator
     s = _sys("p3_k_aniso", 8)
     op = _op(s)
     X = torch.tensor(synth.random_block(1, s.n_dof, 8), device="cuda")
     Y = torch.empty_like(X)
     W = torch.empty_like(X)
-    with pytest.raises(ChfsiError):
-        Batch([(op, 0, X, W)], 4)
     # switching the form clears the operator until set_local runs again
     op.set_form("cell")
     with pytest.raises(ChfsiError):
