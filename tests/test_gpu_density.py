@@ -134,3 +134,35 @@ def test_density_large_workload_sampled_cells():
     er, em = np.abs(got_r - ref_r).max() / scale, np.abs(got_m - ref_m).max() / scale
     print(f"[density scale] {len(cells)} cells: rel err rho {er:.2e} m {em:.2e}", flush=True)
     assert er < 1e-13 and em < 1e-13
+
+
+def test_density_of_a_block_in_a_wider_array_and_argument_checks():
+    """Columns 5..29 of a 40-column array (ld = 40) give the density of that
+    sub-block; bad shapes and sizes are refused before any launch."""
+    import ctypes as C
+    from paper_2410_02754_amd import ChfsiError
+    s = synth.make_system("wide", n_cells=(2, 2, 2), box=(4.0, 4.0, 4.0), p=4, n_atoms=1, lmax=1,
+                          rcut_sigmas=5.0, n_vec=40)
+    op = _op(s)
+    Xw = torch.tensor(synth.random_block(9, s.n_dof, 40), device="cuda")
+    f = _occ(5, 25)
+    r1, m1 = _fields(op)
+    op.density(Xw[:, 5:30], f, r1, m1)
+    r2, m2 = _fields(op)
+    op.density(Xw[:, 5:30].contiguous(), f, r2, m2)
+    assert torch.equal(r1, r2) and torch.equal(m1, m2)
+    with pytest.raises(ValueError):
+        op.density(Xw[:, :25], f, r1[:1], m1)
+    pd = C.POINTER(C.c_double)
+    fo = np.ascontiguousarray(f)
+    rc = op.lib.chfsi_density(op.ctx, C.c_void_p(Xw.data_ptr()), 40, 0, fo.ctypes.data_as(pd),
+                              C.c_void_p(r1.data_ptr()), C.c_void_p(m1.data_ptr()))
+    assert rc == -1
+    rc = op.lib.chfsi_density(op.ctx, C.c_void_p(Xw.data_ptr()), 40, 25, None, C.c_void_p(r1.data_ptr()),
+                              C.c_void_p(m1.data_ptr()))
+    assert rc == -1
+    bad = fo.copy()
+    bad[3] = np.nan
+    with pytest.raises(ChfsiError):
+        op.density(Xw[:, :25], bad, r1, m1)
+    op.close()
