@@ -279,30 +279,37 @@ def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch, tables=None):
     th, r, times, ftimes, fst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "fp64", torch, "matrix-free")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    mixed = None
+    mixed = {}
     if not args.no_mixed:
-        # the residual-form FP32 filter on the same state as the FP64 passes
-        theta, _ = start(op, s, X, W, torch)
-        theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "fp64", torch,
-                                       "matrix-free mixed fp64 warmup")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        thm, rm, _, mft, mst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "mixed", torch,
-                                          "matrix-free mixed_resid", True)
-        torch.cuda.synchronize()
-        mtotal = time.perf_counter() - t1
-        dthm = np.abs(thm - theta_ref)
-        if tables is not None:
-            tables["matrix_free mixed_resid"] = (thm, dthm)
-        mixed = {"form": "residual form, FP32 matrix-free and projector products on the correction",
-                 "s_per_pass": round(mtotal / args.steps, 3),
-                 "filter_s_per_pass": round(sum(mft) / args.steps, 3),
-                 "speedup_pass_vs_matrix_free_fp64": round(total / mtotal, 3),
-                 "max_dtheta_vs_cell_fp64_Ha": float(dthm.max()),
-                 "within_1e-7_Ha": bool(dthm.max() <= 1e-7),
-                 "fp32_launch_ms": round(mst["cell_ms"] / max(1, mst["cell_launches"]), 4),
-                 "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in mst["stage_ms"].items() if v > 0}}
-        log(f"[bench] matrix-free mixed_resid: {mixed['s_per_pass']} s per pass, max |dtheta| {dthm.max():.2e} Ha")
+        # the FP32 filters on the same state as the FP64 passes: plain (applies
+        # 1..m-1 in FP32) and residual form (every correction product in FP32)
+        for key, resid_form, form in (("mixed", False, "applies 1..m-1 with the FP32 matrix-free and projector "
+                                                        "products, apply m FP64"),
+                                      ("mixed_resid", True, "residual form, FP32 matrix-free and projector "
+                                                            "products on the correction")):
+            theta, _ = start(op, s, X, W, torch)
+            theta, _, _, _, _ = run_passes(op, s, X, W, Wf, b, theta, args.warmup, "fp64", torch,
+                                           f"matrix-free {key} fp64 warmup")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            thm, rm, _, mft, mst = run_passes(op, s, X, W, Wf, b, theta, args.steps, "mixed", torch,
+                                              f"matrix-free {key}", resid_form)
+            torch.cuda.synchronize()
+            mtotal = time.perf_counter() - t1
+            dthm = np.abs(thm - theta_ref)
+            if tables is not None:
+                tables[f"matrix_free {key}"] = (thm, dthm)
+            mixed[key] = {"form": form,
+                          "s_per_pass": round(mtotal / args.steps, 3),
+                          "filter_s_per_pass": round(sum(mft) / args.steps, 3),
+                          "speedup_pass_vs_matrix_free_fp64": round(total / mtotal, 3),
+                          "max_dtheta_vs_cell_fp64_Ha": float(dthm.max()),
+                          "within_1e-7_Ha": bool(dthm.max() <= 1e-7),
+                          "fp32_launch_ms": round(mst["cell_ms"] / max(1, mst["cell_launches"]), 4),
+                          "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in mst["stage_ms"].items()
+                                                if v > 0}}
+            log(f"[bench] matrix-free {key}: {mixed[key]['s_per_pass']} s per pass, max |dtheta| "
+                f"{dthm.max():.2e} Ha")
     op.close()
     n_l = max(1, fst["cell_launches"])
     ms = fst["cell_ms"] / n_l
@@ -323,8 +330,7 @@ def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch, tables=None):
            "cell_form_flops_per_launch": fst["cell_flops"] / n_l,
            "max_dtheta_vs_cell_fp64_Ha": float(dth.max()), "max_resid": float(np.max(r)),
            "stage_ms_per_pass": {k: round(v / args.steps, 1) for k, v in fst["stage_ms"].items() if v > 0}}
-    if mixed is not None:
-        res["mixed_resid"] = mixed
+    res.update(mixed)
     log(f"[bench] matrix-free: {res['s_per_pass']} s per pass, max |dtheta| vs cell {dth.max():.2e} Ha")
     return res
 
