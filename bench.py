@@ -41,30 +41,39 @@ K_B_HA = 3.166811563e-6   # Boltzmann constant, Ha / K
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cell_apply_fp64_scale_traffic.md")
 
 
-def cell_kernel_fingerprint():
-    """sha256 over the cell-kernel sources and the device compile flags: a
-    counter record taken for another build of the kernel does not apply."""
+MF_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "mf_apply_density_scale_traffic.md")
+CELL_SOURCES = ("cell.hip", "mfma.h")
+MF_SOURCES = ("matfree.hip", "sumfact.h", "mfma.h")
+
+
+def kernel_fingerprint(sources=CELL_SOURCES):
+    """sha256 over a kernel's sources and the device compile flags: a counter
+    record taken for another build of the kernel does not apply."""
     import hashlib
     from paper_2410_02754_amd import build as b
     h = hashlib.sha256()
-    for f in ("cell.hip", "mfma.h"):
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2410_02754_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     h.update(" ".join(b.COMMON).encode())
     return h.hexdigest()
 
 
-def measured_traffic(grid_wg):
-    """HBM bytes per filter launch of the FP64 cell kernel from the committed
-    counter record (calibrated FETCH_SIZE + WRITE_SIZE), or None when the record
-    is missing, was taken on another launch shape or for other kernel sources."""
+def cell_kernel_fingerprint():
+    return kernel_fingerprint(CELL_SOURCES)
+
+
+def measured_traffic(grid_wg, record=TRAFFIC_RECORD, sources=CELL_SOURCES):
+    """HBM bytes per launch of a kernel from its committed counter record
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None when the record is missing, was
+    taken on another launch shape or for other kernel sources."""
     try:
-        with open(TRAFFIC_RECORD) as fh:
+        with open(record) as fh:
             line = next(l for l in fh if l.startswith("traffic_record: "))
         rec = json.loads(line[len("traffic_record: "):])
     except (OSError, StopIteration, ValueError):
         return None
-    if rec.get("source_sha256") != cell_kernel_fingerprint() or rec.get("grid_wg") != grid_wg:
+    if rec.get("source_sha256") != kernel_fingerprint(sources) or rec.get("grid_wg") != grid_wg:
         return None
     return float(rec["hbm_bytes_per_launch"])
 
@@ -315,7 +324,18 @@ def bench_matfree(args, s, X, W, Wf, b, theta_ref, torch, tables=None):
     ms = fst["cell_ms"] / n_l
     exec_per = fst["cell_exec"] / n_l
     dth = np.abs(th - theta_ref)
+    # roofline of the local operator: algorithmic bytes (rows gathered, output rows read
+    # and written, once per launch) over the mean filter launch
+    n_colour_cells = int(np.prod(s.n_cells)) // 8
+    alg = float(n_colour_cells * 2 * (s.p + 1) ** 3 * s.block * 16 * 3)
+    grid_wg = n_colour_cells * ((s.block + 1) // 2)
+    ach = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM, 4), "algorithmic_bytes_per_launch": alg,
+            "traffic": measured_traffic(grid_wg, MF_TRAFFIC_RECORD, MF_SOURCES),
+            "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)"}
     res = {"form": "matrix-free sum factorisation, FP64 (n_q = p + 1 collocation)",
+           "roofline": roof,
            "s_per_pass": round(total / args.steps, 3),
            "filter_s_per_pass": round(sum(ftimes) / args.steps, 3),
            "filter_tflops_cell_count": round(fst["flops"] / sum(ftimes) / 1e12, 4),
