@@ -556,6 +556,8 @@ def bench_batch(args, torch):
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - t0)
             Yb = [x.clone() for _, _, x, _ in tasks]
+            if prec == "fp64":
+                Yb64 = Yb
             batch.close()
             # the same filters, task by task
             seq = []
@@ -588,6 +590,38 @@ def bench_batch(args, torch):
         batch.close()
         for op in ops:
             op.close()
+        # the same tasks with the matrix-free operator (per-task colour launches
+        # inside the captured filter), same start blocks and bounds
+        mf = {}
+        if not args.no_matfree:
+            t = time.perf_counter()
+            opm = [build_operator(sy, torch, stream, form="matrix_free") for sy in systems]
+            t_setup_mf = time.perf_counter() - t
+            tasks_mf = [(opm[j], ik, X, W) for (_, ik, X, W), (_, j, _) in zip(tasks, meta)]
+            for prec in (("fp64",) if args.no_mixed else ("fp64", "mixed")):
+                batch = Batch(tasks_mf, degree, prec=prec)
+                for _ in range(max(1, args.warmup)):
+                    restore()
+                    batch.filter(a, b, a0)
+                torch.cuda.synchronize()
+                times = []
+                for _ in range(args.steps):
+                    restore()
+                    t0 = time.perf_counter()
+                    batch.filter(a, b, a0)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                batch.close()
+                tb = float(np.median(times))
+                mf[prec] = {"ms_per_filter": round(1e3 * tb, 2),
+                            "speedup_vs_cell_form": round(res[prec]["ms_per_filter"] / (1e3 * tb), 3)}
+                if prec == "fp64":
+                    mf[prec]["max_rel_diff_vs_cell_form"] = max(
+                        float((x - y).abs().max() / y.abs().max()) for (_, _, x, _), y in zip(tasks_mf, Yb64))
+                log(f"[bench] batch matrix-free {prec}: {1e3 * tb:.1f} ms per batched filter")
+            mf["setup_s"] = round(t_setup_mf, 1)
+            for op in opm:
+                op.close()
     f64 = res["fp64"]
     out = {
         "metric": "batched ChFSI filter TFLOP/s (8 k-points + 5 uneven Gamma systems, persistent hipGraph launch)",
@@ -604,6 +638,8 @@ def bench_batch(args, torch):
     if "mixed" in res:
         out["mixed"] = res["mixed"]
         out["speedup_mixed_vs_fp64"] = round(f64["ms_per_filter"] / res["mixed"]["ms_per_filter"], 3)
+    if mf:
+        out["matrix_free"] = mf
     return out
 
 
