@@ -304,10 +304,44 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
     if (!cv[cb]) col[cb] = n_vec - 1;     // clamped: loads stay in bounds
   }
   V4 dr[2][NCB], di[2][NCB];              // [spin][16-column block]
+  // FP64: the recurrence terms start the accumulators, so that their loads are in
+  // flight while the projector back-product runs (lane element j of an
+  // accumulator is node acc_row(lane, j) of the run, column col[cb])
+  constexpr bool kPre = sizeof(T) == 8;
+  const int64_t node0 = (int64_t)run * kNlRun;
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) dr[sp][cb] = di[sp][cb] = V4{0, 0, 0, 0};
+    for (int cb = 0; cb < NCB; ++cb) {
+      dr[sp][cb] = di[sp][cb] = V4{0, 0, 0, 0};
+      if constexpr (kPre) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t node = node0 + acc_row<T>(lane, j);
+          const int64_t row = 2 * (node < n_nodes ? node : n_nodes - 1) + sp;
+          const int c = col[cb];
+          double tr = 0.0, ti = 0.0;
+          if (FL & kInitBeta) {
+            const double2 o = Wold[row * ldo + c];
+            tr += beta * o.x;
+            ti += beta * o.y;
+          }
+          if (FL & kInitGamma) {
+            const double2 xv = X[row * ldx + c];
+            tr += gamma * xv.x;
+            ti += gamma * xv.y;
+          }
+          if (FL & kInitRs) {
+            const double2 rv = Rs[row * ldr + c];
+            const double sc = rscale[c];
+            tr += sc * rv.x;
+            ti += sc * rv.y;
+          }
+          dr[sp][cb][j] = (T)tr;
+          di[sp][cb][j] = (T)ti;
+        }
+      }
+    }
   if (has_nl) {
     const int p0 = run_off[run], p1 = run_off[run + 1];
     for (int pr = p0; pr < p1; ++pr) {
@@ -350,7 +384,6 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
   // lane holds nodes acc_row(lane, j) of the run, columns col[cb]; every load of
   // the epilogue is issued unconditionally (clamped rows) and only the stores
   // are predicated
-  const int64_t node0 = (int64_t)run * kNlRun;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t node = node0 + acc_row<T>(lane, j);
@@ -364,6 +397,10 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
         const int64_t row = 2 * nodec + sp;
         const int c = col[cb];
         double2 t = {(double)dr[sp][cb][j], (double)di[sp][cb][j]};
+        if constexpr (kPre) {
+          v[cb][sp] = t;
+          continue;
+        }
         if (FL & kInitBeta) {
           const double2 o = Wold[row * ldo + c];
           t.x += beta * o.x;
