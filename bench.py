@@ -218,8 +218,9 @@ def main():
                     help="write the per-eigenvalue FP64 / mixed table (text) to this path")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(k-points and systems would go one per GPU; a large system would be split into "
+              "subdomains of cells with halo scatter-adds).", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

@@ -1,7 +1,7 @@
 """Chebyshev-filtered subspace iteration, plain FP64 (paper Sec. III.B.2, eqn:chebfilt
 and the Rayleigh-Ritz projection that follows it).
 
-Readings taken where the paper is silent (also listed in the design doc):
+Readings taken where the paper is silent:
 * the filter uses the scaled three-term recurrence of Zhou, Saad, Tiago and
   Chelikowsky (2006, cited by the paper), which equals T_m(H_s) X divided by the
   scalar T_m((a0 - c)/e), so spans and Ritz values equal the plain form's;
