@@ -745,7 +745,7 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
 // Work item bid -> cell bid % n_cells, column group bid / n_cells, neighbouring
 // cells (which share face nodes) on one XCD.
 constexpr int kQfThreads = 512;
-constexpr int qf_fields(int NP) { return NP <= 8 ? 16 : 8; }
+constexpr int qf_fields(int NP) { return 8; }
 
 template <int NP, int NS>
 __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
