@@ -735,17 +735,17 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
 
 // The same sums with n_q = n_p by sum factorisation.  A workgroup of 512
 // threads owns one cell and a group of columns, and walks the group in chunks of
-// CW columns of NS streams (NF = NS CW fields, one LDS buffer of n_p^3 complex
-// values per field).  Per chunk each thread loads the z-lines of its
-// (column, stream, line) tasks straight into registers (column fastest: eight
-// columns are one 128-byte line of a row), interpolates along z there, and the y
-// and x passes run in place in LDS; the next chunk's z-lines are loaded while the
-// current chunk runs its LDS phases (LDS-only barriers).  Whole lines per row and
-// chunk keep the block's HBM traffic at one read.  tab = the matrix-free tables [B][Dq][w][even-odd tables].
+// CW columns of NS streams (NF = NS CW = 8 fields, one LDS buffer of n_p^3
+// complex values per field: 44 KB at n_p = 7, two workgroups per CU).  Per chunk
+// each thread loads the z-lines of its (column, stream, line) tasks straight into
+// registers (column fastest, so neighbouring lanes read one row), interpolates
+// along z there, and the y and x passes run in place in LDS; the next chunk's
+// z-lines are loaded while the current chunk runs its LDS phases (LDS-only
+// barriers).  tab = the matrix-free tables [B][Dq][w][even-odd tables].
 // Work item bid -> cell bid % n_cells, column group bid / n_cells, neighbouring
 // cells (which share face nodes) on one XCD.
 constexpr int kQfThreads = 512;
-constexpr int qf_fields(int NP) { return 8; }
+constexpr int qf_fields(int) { return 8; }
 
 template <int NP, int NS>
 __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
