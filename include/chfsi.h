@@ -295,20 +295,36 @@ enum chfsi_batch_flags {
   CHFSI_BATCH_AUTOTUNE = 1,  /* time column tile widths 128/64/32 per task at create and keep the
                                 fastest (a narrower width must win by more than 1 %); without it the
                                 widest width <= n_vec is used */
-  CHFSI_BATCH_GRAPH = 2      /* capture the whole filter into a hipGraph and replay it while the bounds
-                                are unchanged (needs a non-default stream) */
+  CHFSI_BATCH_GRAPH = 2      /* capture the whole filter into a hipGraph on the first chfsi_batch_filter
+                                and replay that graph on every later call, whatever the bounds (needs a
+                                non-default stream) */
 };
 
 /* Build a batch of n_tasks tasks for a degree-m filter in precision prec_mode.
  * All contexts must share one stream and have their fields set.  Buffers are
  * bound at creation.  With CHFSI_BATCH_AUTOTUNE the work buffers are used as
- * scratch during creation. */
+ * scratch during creation.  The batch owns the device memory its kernels use
+ * besides the task buffers (projector partial sums, recurrence coefficient
+ * tables), so other calls on the same contexts (chfsi_chol_gs,
+ * chfsi_rayleigh_ritz, ...) may run between filters. */
 int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, int prec_mode, int flags,
                        chfsi_batch** out);
 
 /* Filter every task's block with its own bounds a[t], b[t], a0[t] (host arrays,
- * a0 < a < b): the same scaled recurrence as chfsi_cheb_filter.  Asynchronous. */
+ * a0 < a < b): the same scaled recurrence as chfsi_cheb_filter, bitwise equal to
+ * filtering the tasks one by one.  The recurrence coefficients of all tasks are
+ * copied into a device table before the filter's kernels (which read them from
+ * there), so a captured graph is replayed with new bounds without capturing
+ * again.  Asynchronous.  CHFSI_ESTATE if a task's context has been rebuilt
+ * (chfsi_set_local, chfsi_set_atoms, chfsi_set_apply_form) since
+ * chfsi_batch_create: the batch holds that context's device pointers. */
 int chfsi_batch_filter(chfsi_batch* batch, const double* a, const double* b, const double* a0);
+
+/* Graph statistics of a CHFSI_BATCH_GRAPH batch: number of captures and of
+ * replays, and the accumulated host milliseconds of stream capture and of
+ * graph instantiation.  Any pointer may be NULL. */
+int chfsi_batch_graph_info(const chfsi_batch* batch, int* n_captures, int* n_replays, double* capture_ms,
+                           double* instantiate_ms);
 
 /* Chosen column tile width per task (cols_out[n_tasks]; 0 for a task whose
  * context uses the matrix-free form, which runs its own per-colour launches) and,

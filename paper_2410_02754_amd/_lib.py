@@ -17,7 +17,7 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
             "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
             "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid",
-            "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form"]
+            "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form", "chfsi_batch_graph_info"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -88,6 +88,7 @@ def load():
         "chfsi_batch_filter": ([vp, pd, pd, pd], i32),
         "chfsi_batch_tiles": ([vp, C.POINTER(i32), pd], i32),
         "chfsi_batch_destroy": ([vp], i32),
+        "chfsi_batch_graph_info": ([vp, C.POINTER(i32), C.POINTER(i32), pd, pd], i32),
         "chfsi_batch_last_error": ([vp], C.c_char_p),
         "chfsi_apply_H_backward": ([vp, i32, vp, i64, vp, i64, vp, i64, i32, vp, vp], i32),
         "chfsi_filter_backward_workspace": ([vp, i32, i32, i32], C.c_size_t),

@@ -31,15 +31,17 @@ class ApplyH(torch.autograd.Function):
         X = X.contiguous()
         Y = torch.empty_like(X)
         op.apply_H(X, Y, ik=ik)
-        ctx.save_for_backward(X)
+        ctx.save_for_backward(X, V, B)
         ctx.op, ctx.ik = op, ik
         ctx.shapes = (V.shape, B.shape)
         return Y
 
     @staticmethod
     def backward(ctx, Ybar):
-        (X,) = ctx.saved_tensors
+        X, V, B = ctx.saved_tensors
         op = ctx.op
+        # the operator may have been rebuilt from other fields since the forward
+        _ensure_fields(op, V, B)
         Xbar = torch.empty_like(X)
         dV = torch.zeros(ctx.shapes[0], dtype=torch.float64, device=X.device)
         dB = torch.zeros(ctx.shapes[1], dtype=torch.float64, device=X.device)
@@ -58,7 +60,7 @@ class ChebFilter(torch.autograd.Function):
         Y = X.clone()
         work = torch.empty_like(X)
         op.cheb_filter(Y, work, degree, a, b, a0, ik=ik)
-        ctx.save_for_backward(X)
+        ctx.save_for_backward(X, V, B)
         ctx.op, ctx.ik = op, ik
         ctx.args = (degree, a, b, a0, ckpt_every)
         ctx.shapes = (V.shape, B.shape)
@@ -66,7 +68,9 @@ class ChebFilter(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, Ybar):
-        (X,) = ctx.saved_tensors
+        X, V, B = ctx.saved_tensors
+        # the operator may have been rebuilt from other fields since the forward
+        _ensure_fields(ctx.op, V, B)
         degree, a, b, a0, ck = ctx.args
         Xbar = torch.empty_like(X)
         dV = torch.zeros(ctx.shapes[0], dtype=torch.float64, device=X.device)

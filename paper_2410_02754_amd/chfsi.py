@@ -344,6 +344,15 @@ class Batch:
         self.lib.chfsi_batch_tiles(self.h, cols, ms.ctypes.data_as(C.POINTER(C.c_double)))
         return list(cols), ms.reshape(self.n, 3)
 
+    def graph_info(self) -> dict:
+        """Captures, replays and host milliseconds of capture and instantiation."""
+        nc, nr = C.c_int(), C.c_int()
+        cms, ims = C.c_double(), C.c_double()
+        rc = self.lib.chfsi_batch_graph_info(self.h, C.byref(nc), C.byref(nr), C.byref(cms), C.byref(ims))
+        if rc != 0:
+            raise _lib.ChfsiError(rc, "chfsi_batch_graph_info failed")
+        return {"captures": nc.value, "replays": nr.value, "capture_ms": cms.value, "instantiate_ms": ims.value}
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.chfsi_batch_destroy(self.h)

@@ -6,9 +6,11 @@
 // the cell products of all tasks run as one persistent launch per colour phase
 // (and per tile shape / k-term variant) walking a static item list.  Column
 // tile widths are chosen per task by timing the candidates on the task's own
-// data.  The whole degree-m filter of all tasks is captured into a hipGraph and
-// replayed while the per-task bounds are unchanged.
+// data.  The whole degree-m filter of all tasks is captured into a hipGraph once
+// and replayed for any bounds: every recurrence coefficient is read from device
+// tables that are refreshed before each replay.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -39,14 +41,24 @@ struct chfsi_batch {
   std::vector<double> tune_ms;               // [n_tasks][3] timings of CB = 1, 2, 4 (or -1)
   std::vector<BatchGroup*> groups;
   int max_colours = 0;
-  DevBuf<double> alpha_tab;                  // [degree][n_tasks]
-  std::vector<double> bounds;                // bounds the graph was captured with
+  DevBuf<double> coef_tab;                   // alpha [degree][n_tasks], then (beta, gamma) [degree][n_tasks][2]
+  struct {
+    double* ptr = nullptr;
+  } alpha_tab, bg_tab;                       // views into coef_tab
+  double* coef_h = nullptr;                  // pinned host copy of coef_tab
+  hipEvent_t coef_done = nullptr;            // the last upload of coef_h has been read
+  DevBuf<unsigned char> nl_scratch;          // nonlocal partial sums, shared by the tasks (one stream)
+  std::vector<uint64_t> gen;                 // context generations at creation
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int n_captures = 0, n_replays = 0;
+  double capture_ms = 0.0, instantiate_ms = 0.0;
   std::string last_error;
   ~chfsi_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (coef_done) (void)hipEventDestroy(coef_done);
+    if (coef_h) (void)hipHostFree(coef_h);
     for (auto* g : groups) delete g;
   }
 };
@@ -100,42 +112,32 @@ static void build_items(chfsi_batch* b, BatchGroup& g) {
   CHFSI_HIP(hipStreamSynchronize(b->stream));
 }
 
-// the degree-m filter of every task, enqueued on the batch stream
-static void run_filter(chfsi_batch* b, const std::vector<double>& bounds) {
+// the degree-m filter of every task, enqueued on the batch stream.  Every
+// recurrence coefficient is read from the batch's device tables (alpha_tab,
+// bg_tab), so the enqueued work does not depend on the bounds and one captured
+// graph replays for any bounds.
+static void run_filter(chfsi_batch* b) {
   const int nt = (int)b->tasks.size(), m = b->degree;
-  std::vector<double> al((size_t)(m + 1) * nt), be((size_t)(m + 1) * nt), cc(nt);
-  for (int t = 0; t < nt; ++t) {
-    const double a = bounds[3 * t], bb = bounds[3 * t + 1], a0 = bounds[3 * t + 2];
-    const double e = 0.5 * (bb - a);
-    cc[t] = 0.5 * (bb + a);
-    const double s1 = e / (a0 - cc[t]);
-    double sg = s1;
-    al[(size_t)1 * nt + t] = s1 / e;
-    be[(size_t)1 * nt + t] = 0.0;
-    for (int k = 2; k <= m; ++k) {
-      const double sn = 1.0 / (2.0 / s1 - sg);
-      al[(size_t)k * nt + t] = 2.0 * sn / e;
-      be[(size_t)k * nt + t] = -sg * sn;
-      sg = sn;
-    }
-  }
   for (int k = 1; k <= m; ++k) {
     const int src = (k - 1) & 1;
     const int prec = (b->prec == CHFSI_PREC_MIXED && k < m) ? CHFSI_PREC_MIXED : CHFSI_PREC_FP64;
+    const double* al_k = b->alpha_tab.ptr + (size_t)(k - 1) * nt;
+    const double* bg_k = b->bg_tab.ptr + (size_t)(k - 1) * nt * 2;
     for (int t = 0; t < nt; ++t) {
       const auto& tk = b->tasks[t];
       double2* buf[2] = {(double2*)tk.X_d, (double2*)tk.work_d};
       const int64_t ld[2] = {tk.ldx, tk.ldw};
-      const double a = al[(size_t)k * nt + t];
-      apply_nonlocal_init(tk.ctx, *b->kps[t], buf[src], ld[src], buf[src ^ 1], ld[src ^ 1], tk.n_vec, prec, a,
-                          be[(size_t)k * nt + t], -cc[t] * a);
+      // the host values only select the terms present (k = 1 has no Y_{k-2} term);
+      // the kernels read alpha, beta, gamma from the tables
+      apply_nonlocal_init(tk.ctx, *b->kps[t], buf[src], ld[src], buf[src ^ 1], ld[src ^ 1], tk.n_vec, prec, 1.0,
+                          k == 1 ? 0.0 : 1.0, 1.0, al_k + t, bg_k + 2 * t, b->nl_scratch.ptr);
     }
     for (int col = 0; col < b->max_colours; ++col)
       for (auto* g : b->groups) {
         if (g->n_items[col] == 0) continue;
         launch_cell_batch(b->stream, prec == CHFSI_PREC_FP64, g->cb, g->has_s, g->args, g->items[col]->ptr,
-                          g->n_items[col], b->alpha_tab.ptr + (size_t)(k - 1) * nt + g->chunk * kBatchLaunchTasks,
-                          src, g->grid[prec == CHFSI_PREC_FP64]);
+                          g->n_items[col], al_k + g->chunk * kBatchLaunchTasks, src,
+                          g->grid[prec == CHFSI_PREC_FP64]);
       }
     // matrix-free tasks: their own colour launches, alpha read from the table
     for (int t = 0; t < nt; ++t) {
@@ -144,7 +146,7 @@ static void run_filter(chfsi_batch* b, const std::vector<double>& bounds) {
       double2* buf[2] = {(double2*)tk.X_d, (double2*)tk.work_d};
       const int64_t ld[2] = {tk.ldx, tk.ldw};
       launch_mf_products(tk.ctx, *b->kps[t], prec, buf[src], ld[src], buf[src ^ 1], ld[src ^ 1], tk.n_vec, 0.0,
-                         b->alpha_tab.ptr + (size_t)(k - 1) * nt + t);
+                         al_k + t);
     }
   }
   if (m & 1)
@@ -153,26 +155,35 @@ static void run_filter(chfsi_batch* b, const std::vector<double>& bounds) {
       launch_copy_rows(tk.ctx, (double2*)tk.X_d, tk.ldx, (const double2*)tk.work_d, tk.ldw, 2 * tk.ctx->n_nodes,
                        tk.n_vec);
     }
-  (void)al;
 }
 
-static void upload_alpha(chfsi_batch* b, const std::vector<double>& bounds) {
+// scaled-recurrence coefficients of every task: alpha_k, and (beta_k, gamma_k =
+// -c alpha_k) with Y_k = alpha_k H Y_{k-1} + beta_k Y_{k-2} + gamma_k Y_{k-1}
+static void upload_coeffs(chfsi_batch* b, const std::vector<double>& bounds) {
   const int nt = (int)b->tasks.size(), m = b->degree;
-  std::vector<double> tab((size_t)m * nt);
   for (int t = 0; t < nt; ++t) {
     const double a = bounds[3 * t], bb = bounds[3 * t + 1], a0 = bounds[3 * t + 2];
     const double e = 0.5 * (bb - a), c = 0.5 * (bb + a), s1 = e / (a0 - c);
     double sg = s1;
-    tab[t] = s1 / e;
+    double al = s1 / e;
+    b->coef_h[t] = al;
+    b->coef_h[(size_t)m * nt + 2 * t] = 0.0;
+    b->coef_h[(size_t)m * nt + 2 * t + 1] = -c * al;
     for (int k = 2; k <= m; ++k) {
       const double sn = 1.0 / (2.0 / s1 - sg);
-      tab[(size_t)(k - 1) * nt + t] = 2.0 * sn / e;
+      al = 2.0 * sn / e;
+      b->coef_h[(size_t)(k - 1) * nt + t] = al;
+      b->coef_h[(size_t)m * nt + 2 * ((size_t)(k - 1) * nt + t)] = -sg * sn;
+      b->coef_h[(size_t)m * nt + 2 * ((size_t)(k - 1) * nt + t) + 1] = -c * al;
       sg = sn;
     }
   }
-  CHFSI_HIP(hipMemcpyAsync(b->alpha_tab.ptr, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+  // the host table is pinned memory owned by the batch: the copy is ordered on
+  // the stream before the filter's kernels, and the next upload waits for it
+  CHFSI_HIP(hipEventSynchronize(b->coef_done));
+  CHFSI_HIP(hipMemcpyAsync(b->alpha_tab.ptr, b->coef_h, (size_t)3 * m * nt * sizeof(double), hipMemcpyHostToDevice,
                            b->stream));
-  CHFSI_HIP(hipStreamSynchronize(b->stream));
+  CHFSI_HIP(hipEventRecord(b->coef_done, b->stream));
 }
 
 extern "C" {
@@ -249,6 +260,7 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
     }
     for (auto* g : b->groups) build_items(b, *g);
     std::vector<BatchTaskDev> dt(n_tasks);
+    size_t nl_bytes = 0;
     for (int t = 0; t < n_tasks; ++t) {
       const auto& tk = tasks[t];
       chfsi_ctx* c = tk.ctx;
@@ -266,14 +278,23 @@ int chfsi_batch_create(int n_tasks, const chfsi_batch_task* tasks, int degree, i
       dt[t].nkb = c->nkb;
       dt[t].nmat = kp.nmat;
       dt[t].pad = 0;
-      nonlocal_prepare(c, kp, tk.n_vec);
+      nl_bytes = std::max(nl_bytes, nonlocal_scratch_bytes(kp, tk.n_vec));
+      b->gen.push_back(c->gen);
     }
     for (auto* g : b->groups) {
       g->args = BatchTaskArgs{};
       for (int j = 0; j < kBatchLaunchTasks && g->chunk * kBatchLaunchTasks + j < n_tasks; ++j)
         g->args.t[j] = dt[g->chunk * kBatchLaunchTasks + j];
     }
-    b->alpha_tab.alloc((size_t)degree * n_tasks);
+    // the batch's own device memory: captured kernels hold these pointers, which
+    // no call on the contexts can move
+    b->nl_scratch.alloc(std::max<size_t>(nl_bytes, 16));
+    b->coef_tab.alloc((size_t)3 * degree * n_tasks);
+    b->alpha_tab.ptr = b->coef_tab.ptr;
+    b->bg_tab.ptr = b->coef_tab.ptr + (size_t)degree * n_tasks;
+    CHFSI_HIP(hipHostMalloc((void**)&b->coef_h, (size_t)3 * degree * n_tasks * sizeof(double), hipHostMallocDefault));
+    CHFSI_HIP(hipEventCreateWithFlags(&b->coef_done, hipEventDisableTiming));
+    CHFSI_HIP(hipEventRecord(b->coef_done, b->stream));
     CHFSI_HIP(hipStreamSynchronize(b->stream));
     *out = b;
     return CHFSI_OK;
@@ -303,28 +324,25 @@ int chfsi_batch_filter(chfsi_batch* b, const double* a, const double* bb, const 
       bounds[3 * t + 1] = bb[t];
       bounds[3 * t + 2] = a0[t];
     }
-    upload_alpha(b, bounds);
+    for (int t = 0; t < nt; ++t)
+      CHFSI_CHECK(b->tasks[t].ctx->gen == b->gen[t], CHFSI_ESTATE,
+                  "a task's context was rebuilt (set_local, set_atoms or set_apply_form) after "
+                  "chfsi_batch_create; create the batch again");
+    upload_coeffs(b, bounds);
     if (!(b->flags & CHFSI_BATCH_GRAPH)) {
-      run_filter(b, bounds);
+      run_filter(b);
       return CHFSI_OK;
     }
-    if (!b->exec || bounds != b->bounds) {
-      if (b->exec) {
-        CHFSI_HIP(hipGraphExecDestroy(b->exec));
-        b->exec = nullptr;
-      }
-      if (b->graph) {
-        CHFSI_HIP(hipGraphDestroy(b->graph));
-        b->graph = nullptr;
-      }
+    if (!b->exec) {
       std::vector<bool> stats(nt);
       for (int t = 0; t < nt; ++t) {
         stats[t] = b->tasks[t].ctx->stats_on;
         b->tasks[t].ctx->stats_on = false;   // no event records inside the capture
       }
+      const auto t0 = std::chrono::steady_clock::now();
       CHFSI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
       try {
-        run_filter(b, bounds);
+        run_filter(b);
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(b->stream, &g);
@@ -334,8 +352,14 @@ int chfsi_batch_filter(chfsi_batch* b, const double* a, const double* bb, const 
       }
       CHFSI_HIP(hipStreamEndCapture(b->stream, &b->graph));
       for (int t = 0; t < nt; ++t) b->tasks[t].ctx->stats_on = stats[t];
+      const auto t1 = std::chrono::steady_clock::now();
       CHFSI_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-      b->bounds = bounds;
+      const auto t2 = std::chrono::steady_clock::now();
+      b->capture_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+      b->instantiate_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+      ++b->n_captures;
+    } else {
+      ++b->n_replays;
     }
     CHFSI_HIP(hipGraphLaunch(b->exec, b->stream));
     return CHFSI_OK;
@@ -355,6 +379,16 @@ int chfsi_batch_tiles(const chfsi_batch* b, int* cb_out, double* tune_ms) {
     if (tune_ms)
       for (int j = 0; j < 3; ++j) tune_ms[3 * t + j] = b->tune_ms[3 * t + j];
   }
+  return CHFSI_OK;
+}
+
+int chfsi_batch_graph_info(const chfsi_batch* b, int* n_captures, int* n_replays, double* capture_ms,
+                           double* instantiate_ms) {
+  if (!b) return CHFSI_EINVAL;
+  if (n_captures) *n_captures = b->n_captures;
+  if (n_replays) *n_replays = b->n_replays;
+  if (capture_ms) *capture_ms = b->capture_ms;
+  if (instantiate_ms) *instantiate_ms = b->instantiate_ms;
   return CHFSI_OK;
 }
 

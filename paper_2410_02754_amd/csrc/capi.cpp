@@ -160,6 +160,7 @@ int chfsi_set_apply_form(chfsi_ctx* c, int form) {
   c->mf_qd32.release();
   c->form = form;
   c->have_local = false;
+  ++c->gen;
   API_END(c)
 }
 
@@ -169,6 +170,7 @@ int chfsi_set_local(chfsi_ctx* c, const double* V, const double* B) {
   CHFSI_CHECK(V && B, CHFSI_EINVAL, "veff_d and bxc_d must be non-NULL");
   CHFSI_CHECK(check_finite(c, V, (int64_t)c->n_cells * c->nq3), CHFSI_ENONFINITE, "veff has NaN/Inf");
   CHFSI_CHECK(check_finite(c, B, (int64_t)c->n_cells * c->nq3 * 3), CHFSI_ENONFINITE, "bxc has NaN/Inf");
+  ++c->gen;
   if (c->form == CHFSI_FORM_MATRIX_FREE) {
     mf_set_local(c, V, B);
     c->have_local = true;
@@ -226,6 +228,7 @@ int chfsi_set_atoms(chfsi_ctx* c, int n_atoms, const chfsi_atom_desc* atoms) {
         }
     }
   }
+  ++c->gen;
   for (auto* kp : c->kp) build_nonlocal(c, *kp, n_atoms, atoms);
   API_END(c)
 }
@@ -243,10 +246,8 @@ int chfsi_apply_H(chfsi_ctx* c, int ik, const void* X, int64_t ldx, void* Y, int
   API_END(c)
 }
 
-int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
-                      int degree, double a, double b, double a0, int prec_mode) {
-  if (!c) return CHFSI_EINVAL;
-  API_BEGIN(c)
+static void check_filter_args(chfsi_ctx* c, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec, int degree,
+                              double a, double b, double a0, int prec_mode) {
   require_operator(c);
   check_block(c, X, ldx, n_vec, "X");
   check_block(c, work, ldw, n_vec, "work");
@@ -255,7 +256,11 @@ int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, in
   CHFSI_CHECK(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0) && a0 < a && a < b, CHFSI_EINVAL,
               "filter bounds must satisfy a0 < a < b");
   CHFSI_CHECK(prec_mode == CHFSI_PREC_FP64 || prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL, "unknown precision");
-  KPoint& kp = kpoint(c, ik);
+}
+
+// the scaled recurrence of chfsi_cheb_filter (arguments already checked)
+static void cheb_filter_run(chfsi_ctx* c, KPoint& kp, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
+                            int degree, double a, double b, double a0, int prec_mode) {
   const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
   const double sigma1 = e / (a0 - cc);
   double sigma = sigma1;
@@ -279,6 +284,15 @@ int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, in
     sigma = sn;
   }
   if (cur == 1) launch_copy_rows(c, bufs[0], ldx, bufs[1], ldw, 2 * c->n_nodes, n_vec);
+}
+
+int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
+                      int degree, double a, double b, double a0, int prec_mode) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  check_filter_args(c, X, ldx, work, ldw, n_vec, degree, a, b, a0, prec_mode);
+  KPoint& kp = kpoint(c, ik);
+  cheb_filter_run(c, kp, X, ldx, work, ldw, n_vec, degree, a, b, a0, prec_mode);
   API_END(c)
 }
 

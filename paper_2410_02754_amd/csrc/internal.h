@@ -187,6 +187,9 @@ struct chfsi_ctx {
   std::vector<double> Cgrad[3];               // d-th component of the k-gradient matrix
   std::vector<chfsi::KPoint*> kp;
   bool have_local = false;
+  // bumped by every call that rebuilds device operator data (set_local, set_atoms,
+  // set_apply_form): objects holding its device pointers check it before use
+  uint64_t gen = 0;
   // internal scratch
   chfsi::DevBuf<double> scratch;              // reductions, small matrices
   chfsi::DevBuf<double> panel;                // row panel for in-place rotations
@@ -285,9 +288,15 @@ void launch_cell_batch(hipStream_t s, bool fp64, int CB, bool has_s, const Batch
 int cell_batch_blocks_per_cu(bool fp64, int CB, bool has_s);
 double time_cell_stage(chfsi_ctx* c, KPoint& kp, int CB, int prec, const double2* X, int64_t ldx, double2* W,
                        int64_t ldw, int n_vec, int reps);
-void nonlocal_prepare(chfsi_ctx* c, KPoint& kp, int n_vec);   // size scratch for apply_H of this width
+// bytes of device scratch the nonlocal coefficients of one apply of this width need
+size_t nonlocal_scratch_bytes(const KPoint& kp, int n_vec);
+// W <- beta W + gamma X + alpha H_nl X (nonlocal part and recurrence terms of one
+// apply).  alpha_d, bg_d (device, or null): alpha and (beta, gamma) read at run
+// time; the term flags still follow beta != 0, gamma != 0.  scratch: caller-owned,
+// >= nonlocal_scratch_bytes(kp, n_vec), or null for the context's growable buffer.
 void apply_nonlocal_init(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-                         int n_vec, int prec, double alpha, double beta, double gamma);
+                         int n_vec, int prec, double alpha, double beta, double gamma, const double* alpha_d,
+                         const double* bg_d, void* scratch);
 void launch_fill_random(chfsi_ctx* c, double2* X, int64_t n_rows, int n_vec, int64_t ld,
                         uint64_t seed, int64_t row0, int col0, int64_t n_total_cols);
 }  // namespace chfsi

@@ -190,11 +190,14 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
 }
 
 // Csum[a][r][n] = sum over the chunks of atom a of partial[chunk][r][n] (chunk order fixed)
+// (a column group: partial holds n_vec columns, written to Csum columns col0.. of
+// its ldc-wide rows)
 template <class T>
 __global__ __launch_bounds__(64) void nl_reduce_kernel(const typename C2<T>::type* __restrict__ partial,
                                                        const int32_t* __restrict__ atom_chunk0,
                                                        const int32_t* __restrict__ atom_npj, int max_pj,
-                                                       int n_vec, typename C2<T>::type* __restrict__ Csum) {
+                                                       int n_vec, int ldc, int col0,
+                                                       typename C2<T>::type* __restrict__ Csum) {
   typedef typename C2<T>::type CT;
   const int a = blockIdx.x, r = blockIdx.y;
   const int col = blockIdx.z * 64 + threadIdx.x;
@@ -221,16 +224,19 @@ __global__ __launch_bounds__(64) void nl_reduce_kernel(const typename C2<T>::typ
   CT o;
   o.x = sr;
   o.y = si;
-  Csum[((size_t)a * mr + r) * n_vec + col] = o;
+  Csum[((size_t)a * mr + r) * ldc + col0 + col] = o;
 }
 
-// C'[a][r][n] = alpha sum_r' Delta_a[r][r'] Csum[a][r'][n]
+// C'[a][r][n] = alpha sum_r' Delta_a[r][r'] Csum[a][r'][n]; alpha_d (device, or
+// null) overrides alpha at run time (graph replays with new filter bounds)
 template <class T>
 __global__ __launch_bounds__(64) void nl_delta_kernel(const typename C2<T>::type* __restrict__ Csum,
                                                       const int32_t* __restrict__ atom_npj,
                                                       const double2* __restrict__ delta, int max_pj, int n_vec,
-                                                      double alpha, typename C2<T>::type* __restrict__ Cp) {
+                                                      double alpha, const double* __restrict__ alpha_d,
+                                                      typename C2<T>::type* __restrict__ Cp) {
   typedef typename C2<T>::type CT;
+  if (alpha_d) alpha = *alpha_d;
   const int a = blockIdx.x;
   const int col = blockIdx.y * 64 + threadIdx.x;
   if (col >= n_vec) return;
@@ -273,7 +279,8 @@ __global__ __launch_bounds__(64) void nl_delta_kernel(const typename C2<T>::type
 // loaded before its MFMAs; each coefficient row is read once per run.  W and
 // Wold are not read without the beta term, X without the gamma term, Rs without
 // the residual term (FL: which terms are present).  REALP: real projector values
-// (Gamma point), two real MFMAs per step instead of four.
+// (Gamma point), two real MFMAs per step instead of four.  bg_d (device, or null)
+// overrides (beta, gamma) at run time; FL still selects which terms are read.
 constexpr int kInitBeta = 1, kInitGamma = 2, kInitRs = 4;
 
 template <class T, int FL, bool REALP>
@@ -284,10 +291,14 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
     int has_nl, const double2* __restrict__ X, int64_t ldx, double2* W, int64_t ldw,
     const double2* Wold, int64_t ldo, const double2* __restrict__ Rs, int64_t ldr,
     const double* __restrict__ rscale, int64_t n_nodes, int n_work, int n_coltiles, int n_vec, double beta,
-    double gamma) {
+    double gamma, const double* __restrict__ bg_d) {
   typedef typename C2<T>::type CT;
   typedef typename Vec4<T>::type V4;
   static_assert(kNlRun == 16, "one MFMA row block per run");
+  if (bg_d) {
+    beta = bg_d[0];
+    gamma = bg_d[1];
+  }
   constexpr int KS = (kMaxPj + 3) / 4;    // k-steps per atom
   constexpr int NCB = nl_col_blocks<T>();
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
@@ -429,43 +440,53 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
 
 // Nonlocal coefficients C' = alpha Delta P^H X for every atom; returns the
 // device array [n_atoms][2 max_pj][n_vec] (in the scratch buffer), or null.
+// Scratch: the caller's buffer (scratch, at least nonlocal_scratch_bytes(nl,
+// n_vec) bytes) or the context's growable buffer.  alpha_d as in nl_delta_kernel.
 template <class T>
 static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
                                                    const typename C2<T>::type* proj, const double2* X,
-                                                   int64_t ldx, int n_vec, double alpha) {
+                                                   int64_t ldx, int n_vec, double alpha,
+                                                   const double* alpha_d = nullptr, void* scratch = nullptr) {
   typedef typename C2<T>::type CT;
   if (nl.n_atoms == 0 || nl.n_entries == 0) return nullptr;
   const int mr = 2 * nl.max_pj;
   const size_t n_part = (size_t)nl.n_chunks * mr * n_vec;
   const size_t n_cp = (size_t)nl.n_atoms * mr * n_vec;
   const size_t bytes = (n_part + 2 * n_cp) * sizeof(CT);
-  c->scratch.alloc((bytes + sizeof(double) - 1) / sizeof(double));
-  CT* partial = reinterpret_cast<CT*>(c->scratch.ptr);
-  CT* Csum = partial + n_part;
+  const int group = n_vec;                // columns per contraction launch
+  if (!scratch) {
+    c->scratch.alloc((bytes + sizeof(double) - 1) / sizeof(double));
+    scratch = c->scratch.ptr;
+  }
+  CT* Csum = reinterpret_cast<CT*>(scratch);
   CT* Cp = Csum + n_cp;
+  CT* partial = Cp + n_cp;
   double nl_flops = 0.0;
   for (const auto& at : nl.atoms)
     nl_flops += 2.0 * 8.0 * at.n_sup * at.n_pj * 2.0 * n_vec + 8.0 * 4.0 * at.n_pj * at.n_pj * n_vec;
   const double nl_bytes = (double)nl.n_entries * (2.0 * n_vec * sizeof(double2) + nl.max_pj * sizeof(CT));
   StageTimer tm(c, CHFSI_STAGE_NONLOCAL, nl_flops, nl_flops, nl_bytes);
   const int nct = cdiv(n_vec, 64);
-  const int nct32 = cdiv(n_vec, 16 * nl_col_blocks<T>());
-  const int n_work = nl.n_chunks * nct32;
-  const dim3 cgrid(8 * cdiv(cdiv(n_work, 4), 8));
-  if (nl.real_proj)
-    hipLaunchKernelGGL((nl_contract_kernel<T, true>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
-                       nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
-                       nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X, ldx, n_vec, partial);
-  else
-    hipLaunchKernelGGL((nl_contract_kernel<T, false>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
-                       nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
-                       nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X, ldx, n_vec, partial);
-  LAUNCH_CHECK();
-  hipLaunchKernelGGL(nl_reduce_kernel<T>, dim3(nl.n_atoms, mr, nct), dim3(64), 0, c->stream, partial,
-                     nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.max_pj, n_vec, Csum);
-  LAUNCH_CHECK();
+  for (int c0 = 0; c0 < n_vec; c0 += group) {
+    const int g = std::min(group, n_vec - c0);
+    const int nct32 = cdiv(g, 16 * nl_col_blocks<T>());
+    const int n_work = nl.n_chunks * nct32;
+    const dim3 cgrid(8 * cdiv(cdiv(n_work, 4), 8));
+    if (nl.real_proj)
+      hipLaunchKernelGGL((nl_contract_kernel<T, true>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
+                         nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
+                         nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X + c0, ldx, g, partial);
+    else
+      hipLaunchKernelGGL((nl_contract_kernel<T, false>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
+                         nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
+                         nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X + c0, ldx, g, partial);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(nl_reduce_kernel<T>, dim3(nl.n_atoms, mr, cdiv(g, 64)), dim3(64), 0, c->stream, partial,
+                       nl.atom_chunk0.ptr, nl.atom_npj.ptr, nl.max_pj, g, n_vec, c0, Csum);
+    LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(nl_delta_kernel<T>, dim3(nl.n_atoms, nct), dim3(64), 0, c->stream, Csum,
-                     nl.atom_npj.ptr, nl.delta.ptr, nl.max_pj, n_vec, alpha, Cp);
+                     nl.atom_npj.ptr, nl.delta.ptr, nl.max_pj, n_vec, alpha, alpha_d, Cp);
   LAUNCH_CHECK();
   return Cp;
 }
@@ -475,7 +496,7 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
                                  const typename C2<T>::type* Cp, const double2* X, int64_t ldx,
                                  double2* W, int64_t ldw, const double2* Wold, int64_t ldo, int n_vec,
                                  double beta, double gamma, const double2* Rs = nullptr, int64_t ldr = 0,
-                                 const double* rscale = nullptr) {
+                                 const double* rscale = nullptr, const double* bg_d = nullptr) {
   const int64_t rows = 2 * c->n_nodes;
   StageTimer tm(c, CHFSI_STAGE_AXPY, Cp ? 8.0 * 2.0 * nl.n_entries * nl.max_pj * n_vec : 0.0, 0.0,
                 (double)rows * n_vec * sizeof(double2) * (1.0 + (beta != 0.0) + (gamma != 0.0)));
@@ -488,7 +509,7 @@ static void init_and_backproduct(chfsi_ctx* c, NonlocalK& nl, const typename C2<
 #define INIT_NL_ARGS                                                                                      \
   proj, has ? nl.run_off.ptr : nullptr, has ? nl.pair_atom.ptr : nullptr, has ? nl.pair_ent.ptr : nullptr, \
       has ? nl.atom_npj.ptr : nullptr, nl.max_pj, Cp, has, X, ldx, W, ldw, Wold, ldo, Rs, ldr, rscale,    \
-      c->n_nodes, n_work, nct, n_vec, beta, gamma
+      c->n_nodes, n_work, nct, n_vec, beta, gamma, bg_d
 #define INIT_NL_CASE(F)                                                                        \
   case F:                                                                                      \
     if (has && nl.real_proj)                                                                   \
@@ -567,22 +588,25 @@ void apply_H(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W
 
 // ---------------------------------------------------------------- batched support
 void apply_nonlocal_init(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx, double2* W, int64_t ldw,
-                         int n_vec, int prec, double alpha, double beta, double gamma) {
+                         int n_vec, int prec, double alpha, double beta, double gamma, const double* alpha_d,
+                         const double* bg_d, void* scratch) {
   if (prec == CHFSI_PREC_MIXED) {
-    const float2* Cp = nonlocal_coeffs<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, n_vec, alpha);
-    init_and_backproduct<float>(c, kp.nl, kp.nl.proj32.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma);
+    const float2* Cp = nonlocal_coeffs<float>(c, kp.nl, kp.nl.proj32.ptr, X, ldx, n_vec, alpha, alpha_d, scratch);
+    init_and_backproduct<float>(c, kp.nl, kp.nl.proj32.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma,
+                                nullptr, 0, nullptr, bg_d);
   } else {
-    const double2* Cp = nonlocal_coeffs<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, n_vec, alpha);
-    init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma);
+    const double2* Cp = nonlocal_coeffs<double>(c, kp.nl, kp.nl.proj.ptr, X, ldx, n_vec, alpha, alpha_d, scratch);
+    init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma,
+                                 nullptr, 0, nullptr, bg_d);
   }
 }
 
-void nonlocal_prepare(chfsi_ctx* c, KPoint& kp, int n_vec) {
+size_t nonlocal_scratch_bytes(const KPoint& kp, int n_vec) {
   const NonlocalK& nl = kp.nl;
-  if (nl.n_atoms == 0 || nl.n_entries == 0) return;
+  if (nl.n_atoms == 0 || nl.n_entries == 0) return 0;
   const size_t mr = 2 * nl.max_pj;
   const size_t n = (size_t)nl.n_chunks * mr * n_vec + 2 * (size_t)nl.n_atoms * mr * n_vec;
-  c->scratch.alloc(2 * n);     // double2 elements, the larger of the two precisions
+  return n * sizeof(double2);  // the larger of the two precisions
 }
 
 // ============================================================================

@@ -164,3 +164,44 @@ def test_adjoint_workload_size_closed_form():
     print(f"[adjoint workload] forward {tf:.3f} s backward {tb:.3f} s adjoint identity rel {rel:.2e}")
     assert rel < 1e-10
     op.close()
+
+
+def test_autograd_backward_uses_the_forward_fields():
+    """Two forwards on different fields, then the backward of the first: the
+    adjoint must run with the operator of its own forward (H(V1, B1)), not the
+    one the context holds after the second forward."""
+    from paper_2410_02754_amd.autograd import apply_h, cheb_filter
+    s = SMALL()
+    mesh, H1, MD, Vo, Bo = ham.build(s, synth.veff, synth.bxc)
+    op, V, B = _setup(s)
+    V2 = (1.5 * V + 0.2).contiguous()
+    B2 = (-0.7 * B).contiguous()
+    H2 = ham.build(s, synth.veff, synth.bxc, V=1.5 * Vo + 0.2, B=-0.7 * Bo)[1]
+    lam = np.linalg.eigvalsh(H1.toarray())
+    m, a, b, a0 = 5, float(lam[30]), float(lam[-1] + 2.0), float(lam[0])
+    X0 = synth.random_block(11, s.n_dof, s.n_vec)
+    G0 = synth.random_block(12, s.n_dof, s.n_vec)
+    # apply: Xbar = H1 G
+    X = torch.tensor(X0, device="cuda", requires_grad=True)
+    V1r, B1r = V.clone().requires_grad_(True), B.clone().requires_grad_(True)
+    Y1 = apply_h(X, V1r, B1r, op)
+    Y2 = apply_h(X.detach(), V2, B2, op)
+    Y1.backward(torch.tensor(G0, device="cuda"))
+    ref = H1 @ G0
+    err = np.abs(X.grad.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert np.abs(Y2.detach().cpu().numpy() - H2 @ X0).max() < 1e-12 * np.abs(H2 @ X0).max()
+    print(f"[autograd fields] apply Xbar rel err {err:.2e}")
+    assert err < 1e-12
+    # filter: Xbar, dV, dB of the first forward against the oracle adjoint with H1
+    Xb_o, dV_o, dB_o = oadj.filter_backward(H1, mesh, MD, X0, G0, m, a, b, a0)
+    X = torch.tensor(X0, device="cuda", requires_grad=True)
+    V1r, B1r = V.clone().requires_grad_(True), B.clone().requires_grad_(True)
+    Z1 = cheb_filter(X, V1r, B1r, op, m, a, b, a0, ckpt_every=2)
+    cheb_filter(X.detach(), V2, B2, op, m, a, b, a0)
+    Z1.backward(torch.tensor(G0, device="cuda"))
+    ex = np.abs(X.grad.cpu().numpy() - Xb_o).max() / np.abs(Xb_o).max()
+    ev = np.abs(V1r.grad.cpu().numpy() - dV_o).max() / np.abs(dV_o).max()
+    eb = np.abs(B1r.grad.cpu().numpy() - dB_o).max() / np.abs(dB_o).max()
+    print(f"[autograd fields] filter rel err Xbar {ex:.2e} dV {ev:.2e} dB {eb:.2e}")
+    assert ex < 1e-11 and ev < 1e-11 and eb < 1e-11
+    op.close()

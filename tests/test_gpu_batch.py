@@ -134,3 +134,60 @@ def test_batch_kpoint_parity_and_time_reversal():
             assert d < 1e-9, (i, j, d)
         batch.close()
         op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_graph_replays_across_chfsi_passes(prec):
+    """The ChFSI pass loop with one batch: filter, CholGS + Rayleigh-Ritz on every
+    task (which grows each context's own scratch buffers), filter again with the
+    same bounds and then with new ones.  Every batched filter is bitwise equal to
+    the per-task chfsi_cheb_filter of the same block, and the graph is captured
+    once and replayed for the later passes."""
+    from paper_2410_02754_amd import Batch
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        kg, others = _systems()
+        ops = [_op(kg, stream)] + [_op(s, stream) for s in others]
+        tasks = []
+        for ik in (0, 5):
+            X = torch.tensor(synth.random_block(30 + ik, kg.n_dof, kg.n_vec), device="cuda")
+            tasks.append((ops[0], ik, X, torch.empty_like(X)))
+        for j, s in enumerate(others):
+            X = torch.tensor(synth.random_block(40 + j, s.n_dof, s.n_vec), device="cuda")
+            tasks.append((ops[1 + j], 0, X, torch.empty_like(X)))
+        degree = 7
+        a, b, a0 = [], [], []
+        for op, ik, X, W in tasks:
+            v0 = torch.tensor(synth.lanczos_start(kg, X.shape[0]), device="cuda")
+            lo, hi = op.lanczos_bounds(v0, 20, ik=ik)
+            a.append(lo + 0.3 * (hi - lo)), b.append(hi), a0.append(lo - 0.5)
+        a, b, a0 = np.array(a), np.array(b), np.array(a0)
+        batch = Batch(tasks, degree, prec=prec)
+        for p, (aa, bb, cc) in enumerate([(a, b, a0), (a, b, a0), (0.8 * a + 0.2 * a0, 1.1 * b, a0 - 0.3)]):
+            before = [t[2].clone() for t in tasks]
+            batch.filter(aa, bb, cc)
+            torch.cuda.synchronize()
+            for i, (op, ik, X, W) in enumerate(tasks):
+                Y = before[i].clone()
+                op.cheb_filter(Y, torch.empty_like(Y), degree, aa[i], bb[i], cc[i], ik=ik, prec=prec)
+                torch.cuda.synchronize()
+                assert torch.equal(Y, X), f"pass {p}: task {i} differs from its own filter"
+            # CholGS + RR on every task, as in the pass loop; widens the gram scratch
+            for op, ik, X, W in tasks:
+                op.chol_gs(X)
+                op.rayleigh_ritz(X, W, ik=ik)
+            torch.cuda.synchronize()
+        info = batch.graph_info()
+        print(f"[batch replay {prec}] {info}", flush=True)
+        assert info["captures"] == 1 and info["replays"] == 2
+        # rebuilding a context's operator invalidates the batch
+        pts = ops[1].quad_points().reshape(-1, 3)
+        s1 = others[0]
+        V = torch.tensor(synth.veff(s1, pts).reshape(ops[1].n_cells, ops[1].nq3), device="cuda")
+        B = torch.tensor(synth.bxc(s1, pts).reshape(ops[1].n_cells, ops[1].nq3, 3), device="cuda")
+        ops[1].set_local(V, B)
+        with pytest.raises(Exception, match="CHFSI_ESTATE"):
+            batch.filter(a, b, a0)
+        batch.close()
+        for op in ops:
+            op.close()
