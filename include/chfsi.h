@@ -166,6 +166,28 @@ int chfsi_apply_H(chfsi_ctx* ctx, int ik, const void* X_d, int64_t ldx, void* Y_
 int chfsi_cheb_filter(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
                       int n_vec, int degree, double a, double b, double a0, int prec_mode);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as chfsi_cheb_filter, with the same arguments and the same result
+ * (each column's arithmetic is unchanged), but the nonlocal coefficient
+ * scratch of every apply lives in a fixed device array of
+ * CHFSI_NOALLOC_SCRATCH_BYTES bytes inside the library instead of the
+ * context's growable buffer.  The call issues no hipMalloc/hipFree and no
+ * allocating library routine; X_d and work_d are the caller's as before.
+ * Every context on a device shares that device's one array (held until the
+ * process ends; its address is looked up once per device in chfsi_create):
+ * calls that overlap on one device race, and each call leaves the array's
+ * last contents (nothing in it needs to start at zero).  When the coefficient
+ * arrays and one column of contraction partials do not fit,
+ *   n_chunks * 2 max_pj * 16 + 2 n_atoms * 2 max_pj * n_vec * 16 bytes
+ *   > CHFSI_NOALLOC_SCRATCH_BYTES,
+ * it returns CHFSI_EINVAL before any launch; otherwise the contraction runs
+ * over as many columns per launch as fit.  Stage timers do not record this
+ * call.  Errors as chfsi_cheb_filter. */
+#define CHFSI_NOALLOC_SCRATCH_BYTES (64u << 20)
+int chfsi_cheb_filter_noalloc(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
+                              int n_vec, int degree, double a, double b, double a0, int prec_mode);
+
 /* Ritz residuals in place: W_d[:, i] <- W_d[:, i] - theta_h[i] X_d[:, i] for
  * i < n_vec.  After chfsi_rayleigh_ritz with resid_h non-NULL, work_d holds
  * H_hat X for the rotated X, so this turns it into R = H_hat X - X diag(theta). */

@@ -17,7 +17,8 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_stats_reset", "chfsi_apply_H_backward", "chfsi_filter_backward_workspace",
             "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
             "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid",
-            "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form", "chfsi_batch_graph_info"]
+            "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form", "chfsi_batch_graph_info",
+            "chfsi_cheb_filter_noalloc"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -77,6 +78,7 @@ def load():
         "chfsi_set_atoms": ([vp, i32, C.POINTER(AtomDesc)], i32),
         "chfsi_apply_H": ([vp, i32, vp, i64, vp, i64, i32, i32], i32),
         "chfsi_cheb_filter": ([vp, i32, vp, i64, vp, i64, i32, i32, dbl, dbl, dbl, i32], i32),
+        "chfsi_cheb_filter_noalloc": ([vp, i32, vp, i64, vp, i64, i32, i32, dbl, dbl, dbl, i32], i32),
         "chfsi_chol_gs": ([vp, vp, i64, i32, C.POINTER(i32)], i32),
         "chfsi_rayleigh_ritz": ([vp, i32, vp, i64, vp, i64, i32, pd, pd], i32),
         "chfsi_lanczos_bounds": ([vp, i32, i32, vp, pd, pd], i32),

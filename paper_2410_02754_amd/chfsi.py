@@ -149,6 +149,18 @@ class Operator:
                                              _PREC[prec]))
         return X
 
+    def cheb_filter_noalloc(self, X, work, degree: int, a: float, b: float, a0: float, ik: int = 0,
+                            prec="fp64"):
+        """cheb_filter with the library's fixed nonlocal scratch (no device allocation)."""
+        px, ldx, n = _block(X, "X")
+        pw, ldw, nw = _block(work, "work")
+        if nw < n or X.shape[0] != self.n_dof or work.shape[0] != self.n_dof:
+            raise ValueError("work must be [2M][>= n_vec]")
+        self._chk(self.lib.chfsi_cheb_filter_noalloc(self.ctx, ik, C.c_void_p(px), ldx, C.c_void_p(pw), ldw,
+                                                     n, int(degree), float(a), float(b), float(a0),
+                                                     _PREC[prec]))
+        return X
+
     def ritz_residual(self, X, W, theta):
         """W <- W - X diag(theta) (R = H X - X Theta when W = H X)."""
         px, ldx, n = _block(X, "X")

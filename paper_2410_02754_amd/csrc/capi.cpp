@@ -85,6 +85,8 @@ int chfsi_create(const chfsi_mesh_desc* d, void* stream, chfsi_ctx** out) {
     c->np1 = d->p + 1;
     c->quad = d->quad;
     c->stream = (hipStream_t)stream;
+    CHFSI_HIP(hipGetDevice(&c->device));
+    noalloc_scratch_init();
     c->ref = make_ref(d->p, d->quad, d->n_q);
     c->nq = c->ref.nq;
     build_mesh(c);
@@ -246,8 +248,13 @@ int chfsi_apply_H(chfsi_ctx* c, int ik, const void* X, int64_t ldx, void* Y, int
   API_END(c)
 }
 
-static void check_filter_args(chfsi_ctx* c, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec, int degree,
-                              double a, double b, double a0, int prec_mode) {
+}  // extern "C"
+
+namespace chfsi {
+KPoint& kpoint_of(chfsi_ctx* c, int ik) { return kpoint(c, ik); }
+
+void check_filter_args(chfsi_ctx* c, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec, int degree,
+                       double a, double b, double a0, int prec_mode) {
   require_operator(c);
   check_block(c, X, ldx, n_vec, "X");
   check_block(c, work, ldw, n_vec, "work");
@@ -259,8 +266,8 @@ static void check_filter_args(chfsi_ctx* c, void* X, int64_t ldx, void* work, in
 }
 
 // the scaled recurrence of chfsi_cheb_filter (arguments already checked)
-static void cheb_filter_run(chfsi_ctx* c, KPoint& kp, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
-                            int degree, double a, double b, double a0, int prec_mode) {
+void cheb_filter_run(chfsi_ctx* c, KPoint& kp, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
+                     int degree, double a, double b, double a0, int prec_mode) {
   const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
   const double sigma1 = e / (a0 - cc);
   double sigma = sigma1;
@@ -285,6 +292,9 @@ static void cheb_filter_run(chfsi_ctx* c, KPoint& kp, void* X, int64_t ldx, void
   }
   if (cur == 1) launch_copy_rows(c, bufs[0], ldx, bufs[1], ldw, 2 * c->n_nodes, n_vec);
 }
+}  // namespace chfsi
+
+extern "C" {
 
 int chfsi_cheb_filter(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
                       int degree, double a, double b, double a0, int prec_mode) {

@@ -170,6 +170,7 @@ struct chfsi_ctx {
   int64_t n_nodes;
   int n_cells;
   hipStream_t stream;
+  int device = 0;                             // HIP device current at chfsi_create
   chfsi::RefElement ref;
   // numbering and colouring
   std::vector<int32_t> cell_nodes_h;          // [E][nloc]
@@ -192,6 +193,11 @@ struct chfsi_ctx {
   uint64_t gen = 0;
   // internal scratch
   chfsi::DevBuf<double> scratch;              // reductions, small matrices
+  // when set, the nonlocal coefficients of every apply use this fixed buffer
+  // (nl_fixed_bytes long) instead of growing `scratch`, contracting as many
+  // columns per launch as fit (the allocation-free filter entry point)
+  void* nl_fixed = nullptr;
+  size_t nl_fixed_bytes = 0;
   chfsi::DevBuf<double> panel;                // row panel for in-place rotations
   chfsi::DevBuf<double> cd_partial;           // adjoint cross densities per column group
   chfsi::DevBuf<double> ref_b1, ref_wq;       // 1-D interpolation table and weights (device copy)
@@ -290,6 +296,18 @@ double time_cell_stage(chfsi_ctx* c, KPoint& kp, int CB, int prec, const double2
                        int64_t ldw, int n_vec, int reps);
 // bytes of device scratch the nonlocal coefficients of one apply of this width need
 size_t nonlocal_scratch_bytes(const KPoint& kp, int n_vec);
+// the smallest fixed buffer that serves an apply of this width when the
+// contraction runs one column per launch (the coefficient arrays are whole)
+size_t nonlocal_scratch_bytes_min(const KPoint& kp, int n_vec);
+// the scaled Chebyshev recurrence of chfsi_cheb_filter (arguments checked)
+void check_filter_args(chfsi_ctx* c, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec, int degree,
+                       double a, double b, double a0, int prec_mode);
+void cheb_filter_run(chfsi_ctx* c, KPoint& kp, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
+                     int degree, double a, double b, double a0, int prec_mode);
+KPoint& kpoint_of(chfsi_ctx* c, int ik);
+// looks up this device's copy of the allocation-free entry point's scratch
+// array (once per device; the device must be current)
+void noalloc_scratch_init();
 // W <- beta W + gamma X + alpha H_nl X (nonlocal part and recurrence terms of one
 // apply).  alpha_d, bg_d (device, or null): alpha and (beta, gamma) read at run
 // time; the term flags still follow beta != 0, gamma != 0.  scratch: caller-owned,

@@ -453,8 +453,16 @@ static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
   const size_t n_part = (size_t)nl.n_chunks * mr * n_vec;
   const size_t n_cp = (size_t)nl.n_atoms * mr * n_vec;
   const size_t bytes = (n_part + 2 * n_cp) * sizeof(CT);
-  const int group = n_vec;                // columns per contraction launch
-  if (!scratch) {
+  int group = n_vec;                      // columns per contraction launch
+  if (!scratch && c->nl_fixed) {
+    // fixed buffer: whole coefficient arrays, then as many columns of
+    // partials per contraction launch as fit (the caller checked that one does)
+    const size_t per_col = (size_t)nl.n_chunks * mr * sizeof(CT);
+    const size_t head = 2 * n_cp * sizeof(CT);
+    CHFSI_CHECK(c->nl_fixed_bytes >= head + per_col, CHFSI_EINVAL, "fixed nonlocal scratch too small");
+    group = (int)std::min<size_t>(n_vec, (c->nl_fixed_bytes - head) / per_col);
+    scratch = c->nl_fixed;
+  } else if (!scratch) {
     c->scratch.alloc((bytes + sizeof(double) - 1) / sizeof(double));
     scratch = c->scratch.ptr;
   }
@@ -599,6 +607,13 @@ void apply_nonlocal_init(chfsi_ctx* c, KPoint& kp, const double2* X, int64_t ldx
     init_and_backproduct<double>(c, kp.nl, kp.nl.proj.ptr, Cp, X, ldx, W, ldw, W, ldw, n_vec, beta, gamma,
                                  nullptr, 0, nullptr, bg_d);
   }
+}
+
+size_t nonlocal_scratch_bytes_min(const KPoint& kp, int n_vec) {
+  const NonlocalK& nl = kp.nl;
+  if (nl.n_atoms == 0 || nl.n_entries == 0) return 0;
+  const size_t mr = 2 * nl.max_pj;
+  return ((size_t)nl.n_chunks * mr + 2 * (size_t)nl.n_atoms * mr * n_vec) * sizeof(double2);
 }
 
 size_t nonlocal_scratch_bytes(const KPoint& kp, int n_vec) {
