@@ -296,6 +296,103 @@ int chfsi_fermi_dirac(int n, const double* eps_h, const double* w_h, double n_el
 int chfsi_density(chfsi_ctx* ctx, const void* X_d, int64_t ldx, int n_vec, const double* occ_h,
                   double* rho_d, double* mag_d);
 
+/* ---- Self-consistent field loop (Sec. III.B, eqn:fixedpointmap; Sec. IV.A).
+ * Fields are at the cell quadrature points: scalar fields [E][nq^3] and vector
+ * fields [E][nq^3][3] float64 device arrays in the order of chfsi_quad_points.
+ * The paper's map needs electrostatics and an exchange-correlation functional;
+ * these calls provide stand-ins of the same structure, solved in the FE space
+ * of the context (K_s = int grad N_I . grad N_J, M_c = int N_I N_J with the
+ * cell quadrature; Jacobi-preconditioned conjugate gradients to relative
+ * residual tol, at most max_iter steps; *iters (if non-NULL) receives the step
+ * count, negative when tol was not reached).  All synchronise the stream. */
+
+/* eqn:innerPdt: *out = (1/2)(int r1 r2 + int m1 . m2) (cell quadrature); m1_d,
+ * m2_d both NULL drops the magnetisation part. */
+int chfsi_field_inner(chfsi_ctx* ctx, const double* r1_d, const double* m1_d, const double* r2_d,
+                      const double* m2_d, double* out);
+
+/* Hartree potential with a uniform compensating background (standing in for
+ * the smeared nuclear charges of eqn:poissonEl): -lap V_H = 4 pi (rho - rho_bar)
+ * on the periodic box, V_H of zero mean under the lumped mass M_D, written at
+ * the quadrature points to vh_d (may alias rho_d). */
+int chfsi_hartree(chfsi_ctx* ctx, const double* rho_d, double* vh_d, double tol, int max_iter, int* iters);
+
+/* Kerker preconditioner of a charge residual: out = f - k0^2 w with
+ * (k0^2 - lap) w = f (Fourier factor G^2/(G^2 + k0^2)); k0 = 0 copies f. */
+int chfsi_kerker(chfsi_ctx* ctx, double k0, const double* f_d, double* out_d, double tol, int max_iter,
+                 int* iters);
+
+/* LSDA (Dirac) exchange under the locally collinear substitution of Sec. II.B,
+ * rho_up,dn = (rho +- |m|)/2 (clamped at 0), v_s = -(6/pi)^(1/3) rho_s^(1/3):
+ * vx_d = (v_up + v_dn)/2, bx_d = (v_up - v_dn)/2 m/|m| (0 where m = 0). */
+int chfsi_exchange(chfsi_ctx* ctx, const double* rho_d, const double* m_d, double* vx_d, double* bx_d);
+
+/* Two-grid transfer (Sec. IV.A, eqn:FEWfnsCMesh): the degree-(p-1) spinor fields
+ * of the scaled block Yc_d [2M_c][ldc] on the coarse context, evaluated at the
+ * degree-p nodes of the same cells and written, M_D-scaled, to Yf_d [2M_f][ldf]
+ * of the fine context (fine p = coarse p + 1, same cells and box, same stream). */
+int chfsi_interpolate_block(chfsi_ctx* coarse, chfsi_ctx* fine, const void* Yc_d, int64_t ldc, void* Yf_d,
+                            int64_t ldf, int n_vec);
+
+typedef struct {
+  int n_vec;            /* block width N (all states, one electron each at most)     */
+  int degree;           /* Chebyshev degree                                          */
+  int passes_first;     /* ChFSI passes in the first SCF iteration of the first grid */
+  int passes;           /* ChFSI passes in every other iteration                     */
+  int depth;            /* Anderson history length, 1..16 (1 = linear mixing)        */
+  int max_iter;         /* SCF iterations in total                                   */
+  int max_coarse;       /* iterations on the coarse grid at most                     */
+  int lanczos_steps;    /* Lanczos steps for the upper bound, every iteration        */
+  int field_max_iter;   /* conjugate-gradient steps per field solve at most          */
+  int prec_mode;        /* filter precision, CHFSI_PREC_FP64 or CHFSI_PREC_MIXED     */
+  double n_electrons;   /* 0 < N_e < n_vec                                           */
+  double kT;            /* Fermi-Dirac smearing, Ha                                  */
+  double alpha;         /* mixing parameter                                          */
+  double k0;            /* Kerker wave number, 1/bohr (0: no preconditioning)        */
+  double tol;           /* stop when the residual norm < tol on the fine grid        */
+  double tol_coarse;    /* leave the coarse grid when the residual norm < tol_coarse */
+  double field_tol;     /* relative residual of the field solves                     */
+  uint64_t seed;        /* start block: SplitMix64 stream of chfsi_fill_random       */
+  uint64_t lanczos_seed;/* Lanczos start vector stream                               */
+  const double* bounds_h;/* host [n_bounds]: the filter's upper bound b of iteration i
+                          (a known bound of the spectrum; the Lanczos run is skipped),
+                          or NULL: b from lanczos_steps Lanczos steps every iteration */
+  int n_bounds;         /* entries of bounds_h (iterations past them use Lanczos)    */
+} chfsi_scf_params;
+
+typedef struct {
+  int p;                /* degree of the grid of this iteration                      */
+  double resid;         /* || F(x) - x || in the norm of eqn:innerPdt                */
+  double mu;            /* chemical potential, Ha                                    */
+  double band_energy;   /* sum_n f_n theta_n, Ha                                     */
+  double theta0;        /* lowest Ritz value, Ha                                     */
+  int hartree_iters;    /* conjugate-gradient steps of this iteration's Hartree solve */
+  double b;             /* the filter's upper bound in this iteration, Ha            */
+} chfsi_scf_record;
+
+/* The SCF loop.  Each iteration: V_eff = vext + V_H[rho] + V_x, B_xc = bext + B_x
+ * (chfsi_hartree, chfsi_exchange) set on the grid's context; a Lanczos bound;
+ * on the first iteration of a grid a CholGS + Rayleigh-Ritz prologue; ChFSI
+ * passes (filter with a = max theta, a0 = min theta of the previous RR);
+ * Fermi-Dirac occupations; output densities (chfsi_density) scaled to hold
+ * exactly N_e electrons; residual f = F(x) - x; Anderson mixing: b_j with
+ * sum b_j = 1 minimise || sum b_j f_j || over the last `depth` iterations, and
+ * the next input is sum b_j x_j + alpha (K f_rho, f_m), K = chfsi_kerker.
+ * With coarse non-NULL (degree p-1, same cells, quadrature and stream) the loop
+ * starts there, leaves it when the residual is below tol_coarse (or after
+ * max_coarse iterations), moves the block with chfsi_interpolate_block and
+ * clears the Anderson history; the densities carry over.  Both contexts need
+ * their atoms set; k-point 0 is used.
+ * In/out: rho_d, m_d hold the initial input densities and, on return, the last
+ * input; rho_out_d, m_out_d the last output; X_d [2M][ldx] (fine grid) the last
+ * Ritz block; theta_h[n_vec], occ_h[n_vec] (host, may be NULL) its Ritz values and
+ * occupations; hist_h[max_hist] one record per iteration, *n_hist the count;
+ * *converged 1 if the fine-grid residual fell below tol within max_iter. */
+int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* params, const double* vext_d,
+                  const double* bext_d, double* rho_d, double* m_d, double* rho_out_d, double* m_out_d, void* X_d,
+                  int64_t ldx, double* theta_h, double* occ_h, chfsi_scf_record* hist_h, int max_hist, int* n_hist,
+                  int* converged);
+
 /* ---- Batched filtering of independent operators (the k-points of a grid and
  * independent systems: the eigenproblems of different k are independent,
  * Sec. III.B).  One task = one (context, k-point, block): X_d [2M][ldx] is

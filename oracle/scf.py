@@ -203,7 +203,8 @@ def scf(fine_system, vext, bext, rho0, m0, n_electrons, kT, *, coarse_system=Non
         max_coarse=20, seed=0, lanczos_steps=40, X0=None):
     """Run the SCF loop.  vext [E][nq^3], bext [E][nq^3][3] at the (shared)
     quadrature points; rho0, m0 the initial input densities.  Returns a dict with
-    the history [(degree p of the grid, residual norm, mu, sum f theta, theta_0)], the final
+    the history [(degree p of the grid, residual norm, mu, sum f theta, theta_0, upper bound
+    b of the filter)], the final
     input and output densities, theta and X."""
     import synth
     grids = ([Grid(coarse_system, coarse_system.atoms)] if coarse_system is not None else []) + \
@@ -244,7 +245,7 @@ def scf(fine_system, vext, bext, rho0, m0, n_electrons, kT, *, coarse_system=Non
             rho_out, m_out = q * rho_out, q * m_out
             fr, fm = rho_out - rho_in, m_out - m_in
             nres = float(np.sqrt(inner(g.mesh, fr, fm, fr, fm)))
-            hist.append((g.s.p, nres, mu, float(np.dot(f, theta)), float(theta[0])))
+            hist.append((g.s.p, nres, mu, float(np.dot(f, theta)), float(theta[0]), b))
             conv = nres < (tol if last else tol_coarse)
             if last and (conv or it >= max_iter):
                 return {"history": hist, "rho_in": rho_in, "m_in": m_in, "rho_out": rho_out, "m_out": m_out,

@@ -18,7 +18,8 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_cheb_filter_backward", "chfsi_batch_create", "chfsi_batch_filter", "chfsi_batch_tiles",
             "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid",
             "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form", "chfsi_batch_graph_info",
-            "chfsi_cheb_filter_noalloc"]
+            "chfsi_cheb_filter_noalloc", "chfsi_field_inner", "chfsi_hartree", "chfsi_kerker", "chfsi_exchange",
+            "chfsi_interpolate_block", "chfsi_scf_run"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -38,6 +39,20 @@ class AtomDesc(C.Structure):
 class BatchTask(C.Structure):
     _fields_ = [("ctx", C.c_void_p), ("ik", C.c_int), ("X_d", C.c_void_p), ("ldx", C.c_int64),
                 ("work_d", C.c_void_p), ("ldw", C.c_int64), ("n_vec", C.c_int)]
+
+
+class ScfParams(C.Structure):
+    _fields_ = [("n_vec", C.c_int), ("degree", C.c_int), ("passes_first", C.c_int), ("passes", C.c_int),
+                ("depth", C.c_int), ("max_iter", C.c_int), ("max_coarse", C.c_int), ("lanczos_steps", C.c_int),
+                ("field_max_iter", C.c_int), ("prec_mode", C.c_int), ("n_electrons", C.c_double),
+                ("kT", C.c_double), ("alpha", C.c_double), ("k0", C.c_double), ("tol", C.c_double),
+                ("tol_coarse", C.c_double), ("field_tol", C.c_double), ("seed", C.c_uint64),
+                ("lanczos_seed", C.c_uint64), ("bounds_h", C.POINTER(C.c_double)), ("n_bounds", C.c_int)]
+
+
+class ScfRecord(C.Structure):
+    _fields_ = [("p", C.c_int), ("resid", C.c_double), ("mu", C.c_double), ("band_energy", C.c_double),
+                ("theta0", C.c_double), ("hartree_iters", C.c_int), ("b", C.c_double)]
 
 
 class StageStats(C.Structure):
@@ -99,6 +114,13 @@ def load():
         "chfsi_set_apply_form": ([vp, i32], i32),
         "chfsi_fermi_dirac": ([i32, pd, pd, dbl, dbl, pd, pd, pd], i32),
         "chfsi_density": ([vp, vp, i64, i32, pd, vp, vp], i32),
+        "chfsi_field_inner": ([vp, vp, vp, vp, vp, pd], i32),
+        "chfsi_hartree": ([vp, vp, vp, dbl, i32, C.POINTER(i32)], i32),
+        "chfsi_kerker": ([vp, dbl, vp, vp, dbl, i32, C.POINTER(i32)], i32),
+        "chfsi_exchange": ([vp, vp, vp, vp, vp], i32),
+        "chfsi_interpolate_block": ([vp, vp, vp, i64, vp, i64, i32], i32),
+        "chfsi_scf_run": ([vp, vp, C.POINTER(ScfParams), vp, vp, vp, vp, vp, vp, vp, i64, pd, pd,
+                           C.POINTER(ScfRecord), i32, C.POINTER(i32), C.POINTER(i32)], i32),
         "chfsi_stats_enable": ([vp, i32], i32),
         "chfsi_stats_read": ([vp, C.POINTER(StageStats)], i32),
         "chfsi_stats_reset": ([vp], i32),

@@ -276,6 +276,41 @@ class Operator:
                                          C.c_void_p(rho.data_ptr()), C.c_void_p(mag.data_ptr())))
         return rho, mag
 
+    # ---------------------------------------------------------------- SCF fields
+    def _qfield(self, t, name, vec=False):
+        torch = _torch()
+        shp = (self.n_cells, self.nq3, 3) if vec else (self.n_cells, self.nq3)
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or \
+                not t.is_contiguous() or tuple(t.shape) != shp:
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shp}")
+        return C.c_void_p(t.data_ptr())
+
+    def field_inner(self, r1, m1, r2, m2) -> float:
+        """(1/2)(int r1 r2 + int m1 . m2) with the cell quadrature (m1 = m2 = None: charge part)."""
+        out = C.c_double()
+        pm1 = None if m1 is None else self._qfield(m1, "m1", True)
+        pm2 = None if m2 is None else self._qfield(m2, "m2", True)
+        self._chk(self.lib.chfsi_field_inner(self.ctx, self._qfield(r1, "r1"), pm1, self._qfield(r2, "r2"), pm2,
+                                             C.byref(out)))
+        return out.value
+
+    def hartree(self, rho, vh, tol: float = 1e-13, max_iter: int = 20000) -> int:
+        it = C.c_int()
+        self._chk(self.lib.chfsi_hartree(self.ctx, self._qfield(rho, "rho"), self._qfield(vh, "vh"), float(tol),
+                                         int(max_iter), C.byref(it)))
+        return it.value
+
+    def kerker(self, f, out, k0: float, tol: float = 1e-13, max_iter: int = 20000) -> int:
+        it = C.c_int()
+        self._chk(self.lib.chfsi_kerker(self.ctx, float(k0), self._qfield(f, "f"), self._qfield(out, "out"),
+                                        float(tol), int(max_iter), C.byref(it)))
+        return it.value
+
+    def exchange(self, rho, m, vx, bx):
+        self._chk(self.lib.chfsi_exchange(self.ctx, self._qfield(rho, "rho"), self._qfield(m, "m", True),
+                                          self._qfield(vx, "vx"), self._qfield(bx, "bx", True)))
+        return vx, bx
+
     def stats_enable(self, on: bool = True):
         self._chk(self.lib.chfsi_stats_enable(self.ctx, 1 if on else 0))
 
@@ -291,6 +326,64 @@ class Operator:
 
     def sync(self):
         self._chk(self.lib.chfsi_sync(self.ctx))
+
+
+def interpolate_block(coarse: "Operator", fine: "Operator", Yc, Yf):
+    """Move the degree-(p-1) block Yc of `coarse` to the degree-p nodes of `fine` (into Yf)."""
+    pc, ldc, n = _block(Yc, "Yc")
+    pf, ldf, nf = _block(Yf, "Yf")
+    if nf != n or Yc.shape[0] != coarse.n_dof or Yf.shape[0] != fine.n_dof:
+        raise ValueError("Yc must be [2M_c][n], Yf [2M_f][n]")
+    _lib.check(fine.lib.chfsi_interpolate_block(coarse.ctx, fine.ctx, C.c_void_p(pc), ldc, C.c_void_p(pf), ldf, n),
+               fine.ctx)
+    return Yf
+
+
+SCF_DEFAULTS = dict(passes_first=4, passes=1, depth=4, max_iter=40, max_coarse=20, lanczos_steps=40,
+                    field_max_iter=20000, prec="fp64", alpha=0.5, k0=0.0, tol=1e-8, tol_coarse=1e-3,
+                    field_tol=1e-13, seed=0, lanczos_seed=1, bounds=None)
+
+
+def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons: float, kT: float,
+            degree: int, coarse: Optional["Operator"] = None, max_hist: int = 1000, **kw):
+    """The SCF loop of chfsi_scf_run.  rho, m (in: initial input densities; out: last
+    input), rho_out, m_out (out), X [2M][n_vec] (out: the Ritz block) are CUDA
+    tensors; bounds (optional) the filter's upper bound per iteration.  Returns
+    (history records as dicts, theta, occupations, converged)."""
+    o = dict(SCF_DEFAULTS)
+    unknown = set(kw) - set(o)
+    if unknown:
+        raise TypeError(f"unknown SCF parameters {sorted(unknown)}")
+    o.update(kw)
+    px, ldx, n = _block(X, "X")
+    prm = _lib.ScfParams()
+    prm.n_vec, prm.degree = n, int(degree)
+    for f in ("passes_first", "passes", "depth", "max_iter", "max_coarse", "lanczos_steps", "field_max_iter"):
+        setattr(prm, f, int(o[f]))
+    prm.prec_mode = _PREC[o["prec"]]
+    prm.n_electrons, prm.kT = float(n_electrons), float(kT)
+    for f in ("alpha", "k0", "tol", "tol_coarse", "field_tol"):
+        setattr(prm, f, float(o[f]))
+    prm.seed, prm.lanczos_seed = int(o["seed"]), int(o["lanczos_seed"])
+    bnd = None
+    if o["bounds"] is not None:
+        bnd = np.ascontiguousarray(np.asarray(o["bounds"], dtype=np.float64).reshape(-1))
+        prm.bounds_h = bnd.ctypes.data_as(C.POINTER(C.c_double))
+        prm.n_bounds = bnd.shape[0]
+    th = np.zeros(n)
+    occ = np.zeros(n)
+    hist = (_lib.ScfRecord * max_hist)()
+    nh, conv = C.c_int(), C.c_int()
+    pd = C.POINTER(C.c_double)
+    rc = fine.lib.chfsi_scf_run(fine.ctx, None if coarse is None else coarse.ctx, C.byref(prm),
+                                fine._qfield(vext, "vext"), fine._qfield(bext, "bext", True),
+                                fine._qfield(rho, "rho"), fine._qfield(m, "m", True),
+                                fine._qfield(rho_out, "rho_out"), fine._qfield(m_out, "m_out", True),
+                                C.c_void_p(px), ldx, th.ctypes.data_as(pd), occ.ctypes.data_as(pd), hist,
+                                int(max_hist), C.byref(nh), C.byref(conv))
+    _lib.check(rc, fine.ctx)
+    recs = [{f: getattr(hist[i], f) for f, _ in _lib.ScfRecord._fields_} for i in range(min(nh.value, max_hist))]
+    return recs, th, occ, bool(conv.value)
 
 
 BATCH_AUTOTUNE = 1

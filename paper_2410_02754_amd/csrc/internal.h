@@ -5,6 +5,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -152,6 +153,8 @@ struct BatchTaskArgs {
   BatchTaskDev t[kBatchLaunchTasks];
 };
 
+struct FieldOps;   // SCF field solves (fields.hip)
+
 struct StageRec {
   int stage;
   hipEvent_t start, stop;
@@ -209,6 +212,8 @@ struct chfsi_ctx {
   chfsi::DevBuf<double> mf_qd;                // [E][nq^3][4]: w_q J (V, Bx, By, Bz)
   chfsi::DevBuf<float> mf_tab32, mf_qd32;     // FP32 copies for mixed precision
   chfsi::DevBuf<float> mf_kin32;              // [3][nq^3] FP32 kinetic weights per point
+  // tables and work vectors of the SCF field solves (built on first use)
+  std::shared_ptr<chfsi::FieldOps> fields;
   // stage timing
   bool stats_on = false;
   std::vector<chfsi::StageRec> pending;
@@ -305,6 +310,17 @@ void check_filter_args(chfsi_ctx* c, void* X, int64_t ldx, void* work, int64_t l
 void cheb_filter_run(chfsi_ctx* c, KPoint& kp, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
                      int degree, double a, double b, double a0, int prec_mode);
 KPoint& kpoint_of(chfsi_ctx* c, int ik);
+// SCF fields (fields.hip): integrals and the eqn:innerPdt product at the
+// quadrature points, screened Poisson solves, exchange, the two-grid transfer
+double field_integral(chfsi_ctx* c, const double* g);
+double field_inner(chfsi_ctx* c, const double* r1, const double* m1, const double* r2, const double* m2);
+int screened_poisson(chfsi_ctx* c, double kappa2, double scale, const double* g, double* u_q, double tol,
+                     int max_iter, double* rel);
+void launch_exchange(chfsi_ctx* c, int64_t n_points, const double* rho, const double* m, const double* vadd,
+                     const double* badd, double* V, double* B);
+void field_axpby(chfsi_ctx* c, int64_t n, double a, const double* x, double b, const double* y, double* out);
+void interpolate_block(chfsi_ctx* cc, chfsi_ctx* cf, const double2* Yc, int64_t ldc, double2* Yf, int64_t ldf,
+                       int n_vec);
 // looks up this device's copy of the allocation-free entry point's scratch
 // array (once per device; the device must be current)
 void noalloc_scratch_init();
