@@ -399,6 +399,8 @@ void field_axpby(chfsi_ctx* c, int64_t n, double a, const double* x, double b, c
   axpby(c, n, a, x, b, y, out);
 }
 
+void field_fill(chfsi_ctx* c, int64_t n, double v, double* out) { fill(c, n, v, out); }
+
 void interpolate_block(chfsi_ctx* cc, chfsi_ctx* cf, const double2* Yc, int64_t ldc, double2* Yf, int64_t ldf,
                        int n_vec) {
   std::vector<double> T, D;

@@ -318,7 +318,9 @@ int screened_poisson(chfsi_ctx* c, double kappa2, double scale, const double* g,
                      int max_iter, double* rel);
 void launch_exchange(chfsi_ctx* c, int64_t n_points, const double* rho, const double* m, const double* vadd,
                      const double* badd, double* V, double* B);
+// out = a x + b y (y may be null: out = a x; a NaN in y propagates even if b = 0)
 void field_axpby(chfsi_ctx* c, int64_t n, double a, const double* x, double b, const double* y, double* out);
+void field_fill(chfsi_ctx* c, int64_t n, double v, double* out);
 void interpolate_block(chfsi_ctx* cc, chfsi_ctx* cf, const double2* Yc, int64_t ldc, double2* Yf, int64_t ldf,
                        int n_vec);
 // looks up this device's copy of the allocation-free entry point's scratch

@@ -1176,78 +1176,86 @@ void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t
 }
 
 // X[r0 + r][:] = P[r][:] Q over a row panel P (a copy of those rows).  upper:
-// Q[k][j] = 0 for k > j, so the k range of a column tile ends at its last column.
-// Work item = (row tile, column tile), column tile fastest and consecutive on one
-// XCD, so the column tiles of one row tile read its panel rows through one L2.
+// Q[k][j] = 0 for k > j, so the k range of a column tile ends at its last column;
+// a workgroup then takes column tiles ct and n_ct - 1 - ct of its row tile in turn
+// (equal work per workgroup: the k ranges of the pair add up to n + kGN).
+// Work item = (row tile, column tile or pair), consecutive on one XCD, so the
+// column tiles of one row tile read its panel rows through one L2.
 __global__ __launch_bounds__(256) void rotate_kernel(const double2* __restrict__ P, int n,
                                                      int64_t prow, const double2* __restrict__ Q,
                                                      double2* __restrict__ X, int64_t ldx, int upper,
                                                      int n_rt, int n_ct) {
   __shared__ GemmSmem sm;
-  const int n_work = n_rt * n_ct;
+  const int n_cw = upper ? (n_ct + 1) / 2 : n_ct;    // column work items per row tile
+  const int n_work = n_rt * n_cw;
   const int per_xcd = (int)((gridDim.x + 7) / 8);
   const int bid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
   if (bid >= n_work) return;              // uniform over the block, before any barrier
-  const int rt = bid / n_ct, ct = bid - rt * n_ct;
+  const int rt = bid / n_cw, cw = bid - rt * n_cw;
   const int64_t r0 = (int64_t)rt * kGM;
-  const int j0 = ct * kGN;
-  const int kend = upper ? std::min(n, j0 + kGN) : n;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave & 1, wn = wave >> 1;
   // staging map: A 128 panel rows x 8 k (4 consecutive k per thread, stored
   // k-major), B 8 rows of Q x 64 columns (columns (tid & 31) + 32 u)
   const int am = tid >> 1, ak = (tid & 1) * 4;
   const int bk = tid >> 5, bn = tid & 31;
-  d4 cr[4][2], ci[4][2];
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) cr[mb][nb] = ci[mb][nb] = d4{0, 0, 0, 0};
-  double2 pa[4], pb[2];
   const int64_t ra = r0 + am;
   const bool rav = ra < prow;
   const double2* prow_p = P + (rav ? ra : 0) * (int64_t)n;
-  auto gload = [&](int k0) {
+  const int n_pass = (upper && n_ct - 1 - cw != cw) ? 2 : 1;
+  for (int pass = 0; pass < n_pass; ++pass) {
+    const int ct = pass == 0 ? cw : n_ct - 1 - cw;
+    const int j0 = ct * kGN;
+    const int kend = upper ? std::min(n, j0 + kGN) : n;
+    d4 cr[4][2], ci[4][2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + ak + u;
-      pa[u] = (rav && k < kend) ? prow_p[k] : double2{0.0, 0.0};
-    }
-    const int kb = k0 + bk;
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int cj = j0 + bn + 32 * u;
-      pb[u] = (kb < kend && cj < n) ? Q[(size_t)kb * n + cj] : double2{0.0, 0.0};
-    }
-  };
-  auto lstore = [&](int buf) {
+      for (int nb = 0; nb < 2; ++nb) cr[mb][nb] = ci[mb][nb] = d4{0, 0, 0, 0};
+    double2 pa[4], pb[2];
+    auto gload = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sm.a[buf][ak + u][am] = pa[u];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + 32 * u] = pb[u];
-  };
-  const int nst = (kend + kGK - 1) / kGK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int buf = st & 1;
-    const bool more = st + 1 < nst;
-    if (more) gload((st + 1) * kGK);
-    gemm_stage<false>(sm, buf, wm, wn, lane, cr, ci);
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t r = r0 + wm * 64 + mb * 16 + acc_row<double>(lane, j);
-        const int cj = j0 + wn * 32 + nb * 16 + (lane & 15);
-        if (r < prow && cj < n) X[r * ldx + cj] = double2{cr[mb][nb][j], ci[mb][nb][j]};
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + ak + u;
+        pa[u] = (rav && k < kend) ? prow_p[k] : double2{0.0, 0.0};
       }
+      const int kb = k0 + bk;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int cj = j0 + bn + 32 * u;
+        pb[u] = (kb < kend && cj < n) ? Q[(size_t)kb * n + cj] : double2{0.0, 0.0};
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sm.a[buf][ak + u][am] = pa[u];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) sm.b[buf][bk][bn + 32 * u] = pb[u];
+    };
+    const int nst = (kend + kGK - 1) / kGK;
+    if (pass > 0) __syncthreads();          // the previous tile's last stage has read sm
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st & 1;
+      const bool more = st + 1 < nst;
+      if (more) gload((st + 1) * kGK);
+      gemm_stage<false>(sm, buf, wm, wn, lane, cr, ci);
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t r = r0 + wm * 64 + mb * 16 + acc_row<double>(lane, j);
+          const int cj = j0 + wn * 32 + nb * 16 + (lane & 15);
+          if (r < prow && cj < n) X[r * ldx + cj] = double2{cr[mb][nb][j], ci[mb][nb][j]};
+        }
+  }
 }
 
 void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n, const std::vector<cplx>& Q,
@@ -1268,7 +1276,8 @@ void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n, 
     const int64_t pr = std::min(prow, rows - r0);
     launch_copy_rows(c, P, n, X + r0 * ldx, ldx, pr, n);
     const int n_rt = cdiv(pr, kGM), n_ct = cdiv(n, kGN);
-    const int grid = 8 * cdiv((int64_t)n_rt * n_ct, 8);
+    const int n_cw = upper ? (n_ct + 1) / 2 : n_ct;
+    const int grid = 8 * cdiv((int64_t)n_rt * n_cw, 8);
     hipLaunchKernelGGL(rotate_kernel, dim3(grid), dim3(256), 0, c->stream, P, n, pr, Qd, X + r0 * ldx, ldx,
                        upper ? 1 : 0, n_rt, n_ct);
     LAUNCH_CHECK();

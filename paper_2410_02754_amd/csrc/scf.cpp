@@ -246,8 +246,8 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
         double mu = 0.0;
         check_rc(chfsi_fermi_dirac(N, theta.data(), nullptr, P.n_electrons, P.kT, occ.data(), &mu, nullptr), nullptr,
                  "scf_run: occupations");
-        field_axpby(c, np, 0.0, ro.ptr, 0.0, nullptr, ro.ptr);
-        field_axpby(c, 3 * np, 0.0, mo.ptr, 0.0, nullptr, mo.ptr);
+        field_fill(c, np, 0.0, ro.ptr);
+        field_fill(c, 3 * np, 0.0, mo.ptr);
         check_rc(chfsi_density(g, Xg, ldg, N, occ.data(), ro.ptr, mo.ptr), g, "scf_run: densities");
         // hold exactly N_e electrons under the cell quadrature
         const double q = P.n_electrons / field_integral(c, ro.ptr);
