@@ -627,6 +627,9 @@ def bench_scale(args, torch):
         "theta_min": float(theta64[0]), "theta_max": float(theta64[-1]), "max_resid": float(np.max(r64)),
     }
 
+    # orthonormality of the final Ritz block (CholGS, then the unitary RR rotation)
+    G = op.overlap(X, X)
+    out["orthonormality_max_abs_XhX_minus_I"] = float(np.abs(G - np.eye(s.n_vec)).max())
     out["density"] = bench_density(op, s, X, theta64, torch)
 
     tables = {}
@@ -851,7 +854,80 @@ def bench_batch(args, torch):
         out["speedup_mixed_vs_fp64"] = round(f64["ms_per_filter"] / res["mixed"]["ms_per_filter"], 3)
     if mf:
         out["matrix_free"] = mf
+    out["small_systems"] = bench_small_batch(args, torch)
     return out
+
+
+def bench_small_batch(args, torch, n_sys=32):
+    """A batch of many small independent systems, where launches rather than
+    bandwidth bound each task's filter: n_sys periodic 3^3-cell p=4 systems
+    (3456 dofs, 2 SOC atoms l<=1, N=32, seeds 10..), degree 10, filtered by one
+    replayed graph (persistent cell-product launch per colour phase) against the
+    same filters issued task by task."""
+    import synth
+    from paper_2410_02754_amd import Batch
+    stream = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(stream):
+        systems = [synth.make_system(f"small{i}", seed=10 + i) for i in range(n_sys)]
+        ops = [build_operator(sy, torch, stream) for sy in systems]
+        tasks, a, b, a0 = [], [], [], []
+        for op, sy in zip(ops, systems):
+            X = torch.empty((sy.n_dof, sy.n_vec), dtype=torch.complex128, device="cuda")
+            W = torch.empty_like(X)
+            op.fill_random(X, sy.seed, n_total_cols=sy.n_vec)
+            v0 = torch.empty((sy.n_dof, 1), dtype=torch.complex128, device="cuda")
+            op.fill_random(v0, sy.seed + 1)
+            _, hi = op.lanczos_bounds(v0[:, 0], 40)
+            op.chol_gs(X)
+            theta, _ = op.rayleigh_ritz(X, W)
+            a.append(float(theta[-1]))
+            a0.append(float(theta[0]))
+            b.append(hi)
+            tasks.append((op, 0, X, W))
+        X0 = [x.clone() for _, _, x, _ in tasks]
+        degree = systems[0].degree
+
+        def restore():
+            for (_, _, X, _), x0 in zip(tasks, X0):
+                X.copy_(x0)
+            torch.cuda.synchronize()
+
+        for prec in ("fp64", "mixed"):
+            batch = Batch(tasks, degree, prec=prec)
+            for _ in range(max(1, args.warmup)):
+                restore()
+                batch.filter(a, b, a0)
+            tb = []
+            for _ in range(max(3, args.steps)):
+                restore()
+                t0 = time.perf_counter()
+                batch.filter(a, b, a0)
+                torch.cuda.synchronize()
+                tb.append(time.perf_counter() - t0)
+            Yb = [x.clone() for _, _, x, _ in tasks]
+            info = batch.graph_info()
+            batch.close()
+            ts = []
+            for _ in range(max(3, args.steps)):
+                restore()
+                t0 = time.perf_counter()
+                for (op, ik, X, W), aa, bb, cc in zip(tasks, a, b, a0):
+                    op.cheb_filter(X, W, degree, aa, bb, cc, prec=prec)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            same = all(bool(torch.equal(y, x)) for y, (_, _, x, _) in zip(Yb, tasks))
+            tbm, tsm = float(np.median(tb)), float(np.median(ts))
+            res[prec] = {"ms_per_batched_filter": round(1e3 * tbm, 3), "sequential_ms": round(1e3 * tsm, 3),
+                         "speedup_vs_sequential": round(tsm / tbm, 3), "bitwise_equal_to_sequential": same,
+                         "graph": info}
+            log(f"[bench] small-system batch {prec}: {1e3 * tbm:.2f} ms batched, {1e3 * tsm:.2f} ms task by task "
+                f"({tsm / tbm:.2f}x), bitwise equal {same}")
+        for op in ops:
+            op.close()
+    res["workload"] = (f"{n_sys} independent periodic 3^3-cell p=4 systems (3456 dofs, 2 SOC atoms l<=1, "
+                       f"N=32), degree {degree}")
+    return res
 
 
 def _adjoint_run(args, s, op, torch):

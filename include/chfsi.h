@@ -212,7 +212,8 @@ int chfsi_cheb_filter_resid(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, cons
 
 /* Cholesky-Gram-Schmidt: S = X^H X (FP64), S = L L^H, X <- X L^{-H}, so that
  * the columns become orthonormal with the same span (the orthonormalisation
- * before the Rayleigh-Ritz step, Sec. III.B.2).  On CHFSI_ENOTPD *bad_col (if
+ * before the Rayleigh-Ritz step, Sec. III.B.2).  The factorisation runs on the
+ * unit-diagonal D S D, D = diag(S)^{-1/2} (same result in exact arithmetic).  On CHFSI_ENOTPD *bad_col (if
  * non-NULL) is the first column whose pivot is not positive and X is left
  * unchanged. */
 int chfsi_chol_gs(chfsi_ctx* ctx, void* X_d, int64_t ldx, int n_vec, int* bad_col);
@@ -225,6 +226,21 @@ int chfsi_chol_gs(chfsi_ctx* ctx, void* X_d, int64_t ldx, int n_vec, int* bad_co
  * throughout. */
 int chfsi_rayleigh_ritz(chfsi_ctx* ctx, int ik, void* X_d, int64_t ldx, void* work_d, int64_t ldw,
                         int n_vec, double* ritz_h, double* resid_h);
+
+/* Overlap S = X^H Y of two blocks [2M][ldx], [2M][ldy] of n_vec columns (FP64
+ * MFMA Gram, fixed-order reduction): S_h host [n_vec][n_vec] complex128, row-major
+ * (S_h[i][j] = x_i^H y_j).  Synchronises the stream.  For checks such as the
+ * orthonormality ||X^H X - I|| after chfsi_chol_gs. */
+int chfsi_overlap(chfsi_ctx* ctx, const void* X_d, int64_t ldx, const void* Y_d, int64_t ldy, int n_vec,
+                  double* S_h);
+
+/* Device memory the library itself holds for one call of the given kind on a
+ * block of n_vec columns at k-point ik (its growable scratch, the rotation panel,
+ * partial sums), excluding the caller's buffers (X, work, the backward
+ * workspace): the peak of the call, in bytes; 0 for invalid arguments. */
+enum chfsi_op { CHFSI_OP_APPLY = 0, CHFSI_OP_FILTER = 1, CHFSI_OP_CHOL_GS = 2, CHFSI_OP_RAYLEIGH_RITZ = 3,
+                CHFSI_OP_DENSITY = 4 };
+size_t chfsi_workspace_bytes(const chfsi_ctx* ctx, int ik, int n_vec, int op);
 
 /* Spectral bounds by `steps` Lanczos steps on H_hat^k from v0_d [2M]
  * (complex128, device, not modified): *lo = smallest Ritz value of the

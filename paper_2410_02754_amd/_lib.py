@@ -19,7 +19,7 @@ EXPORTED = ["chfsi_create", "chfsi_destroy", "chfsi_sizes", "chfsi_quad_points",
             "chfsi_batch_destroy", "chfsi_batch_last_error", "chfsi_ritz_residual", "chfsi_cheb_filter_resid",
             "chfsi_fermi_dirac", "chfsi_density", "chfsi_set_apply_form", "chfsi_batch_graph_info",
             "chfsi_cheb_filter_noalloc", "chfsi_field_inner", "chfsi_hartree", "chfsi_kerker", "chfsi_exchange",
-            "chfsi_interpolate_block", "chfsi_scf_run"]
+            "chfsi_interpolate_block", "chfsi_scf_run", "chfsi_overlap", "chfsi_workspace_bytes"]
 
 STAGES = ["cell_fp64", "cell_fp32", "nonlocal", "axpy", "gram", "rotate", "host_dense"]
 
@@ -115,6 +115,8 @@ def load():
         "chfsi_fermi_dirac": ([i32, pd, pd, dbl, dbl, pd, pd, pd], i32),
         "chfsi_density": ([vp, vp, i64, i32, pd, vp, vp], i32),
         "chfsi_field_inner": ([vp, vp, vp, vp, vp, pd], i32),
+        "chfsi_overlap": ([vp, vp, i64, vp, i64, i32, pd], i32),
+        "chfsi_workspace_bytes": ([vp, i32, i32, i32], C.c_size_t),
         "chfsi_hartree": ([vp, vp, vp, dbl, i32, C.POINTER(i32)], i32),
         "chfsi_kerker": ([vp, dbl, vp, vp, dbl, i32, C.POINTER(i32)], i32),
         "chfsi_exchange": ([vp, vp, vp, vp, vp], i32),

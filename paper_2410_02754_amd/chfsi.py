@@ -196,6 +196,23 @@ class Operator:
             raise err
         return X
 
+    def overlap(self, X, Y) -> np.ndarray:
+        """S = X^H Y (host complex128 [n][n])."""
+        px, ldx, n = _block(X, "X")
+        py, ldy, ny = _block(Y, "Y")
+        if ny != n:
+            raise ValueError("X and Y must have the same width")
+        S = np.zeros((n, n), dtype=np.complex128)
+        self._chk(self.lib.chfsi_overlap(self.ctx, C.c_void_p(px), ldx, C.c_void_p(py), ldy, n,
+                                         S.ctypes.data_as(C.POINTER(C.c_double))))
+        return S
+
+    def workspace_bytes(self, n_vec: int, op: str, ik: int = 0) -> int:
+        """Device bytes the library holds for one call ("apply", "filter", "chol_gs",
+        "rayleigh_ritz", "density") on n_vec columns."""
+        ops = {"apply": 0, "filter": 1, "chol_gs": 2, "rayleigh_ritz": 3, "density": 4}
+        return int(self.lib.chfsi_workspace_bytes(self.ctx, int(ik), int(n_vec), ops[op]))
+
     def rayleigh_ritz(self, X, work, ik: int = 0, resid: bool = True):
         px, ldx, n = _block(X, "X")
         pw, ldw, nw = _block(work, "work")

@@ -396,6 +396,21 @@ int chfsi_chol_gs(chfsi_ctx* c, void* X, int64_t ldx, int n_vec, int* bad_col) {
   for (const auto& v : S)
     CHFSI_CHECK(std::isfinite(v.real()) && std::isfinite(v.imag()), CHFSI_ENONFINITE, "Gram matrix has NaN/Inf");
   auto t0 = std::chrono::steady_clock::now();
+  // diagonal pre-scaling: S' = D S D with D = diag(S)^{-1/2} (unit diagonal), S' = L' L'^H,
+  // X <- X D L'^{-H}.  In exact arithmetic D^{-1} L' is the Cholesky factor of S, so the
+  // result is the unscaled one; columns of very different norms no longer set the
+  // factor's conditioning.
+  std::vector<double> dsc(n_vec);
+  for (int j = 0; j < n_vec; ++j) {
+    const double sjj = S[(size_t)j * n_vec + j].real();
+    if (!(sjj > 0.0)) {
+      if (bad_col) *bad_col = j;
+      throw Error{CHFSI_ENOTPD, "Gram matrix not positive definite at column " + std::to_string(j)};
+    }
+    dsc[j] = 1.0 / std::sqrt(sjj);
+  }
+  for (int i = 0; i < n_vec; ++i)
+    for (int j = 0; j < n_vec; ++j) S[(size_t)i * n_vec + j] *= dsc[i] * dsc[j];
   const int bad = cholesky_lower(S, n_vec);
   if (bad >= 0) {
     if (bad_col) *bad_col = bad;
@@ -404,11 +419,60 @@ int chfsi_chol_gs(chfsi_ctx* c, void* X, int64_t ldx, int n_vec, int* bad_col) {
   std::vector<cplx> Linv, R((size_t)n_vec * n_vec);
   lower_inverse(S, n_vec, Linv);
   for (int i = 0; i < n_vec; ++i)
-    for (int j = 0; j < n_vec; ++j) R[(size_t)i * n_vec + j] = std::conj(Linv[(size_t)j * n_vec + i]);
+    for (int j = 0; j < n_vec; ++j) R[(size_t)i * n_vec + j] = dsc[i] * std::conj(Linv[(size_t)j * n_vec + i]);
   stats_add_host(c, CHFSI_STAGE_HOST_DENSE,
                  std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   rotate_inplace(c, (double2*)X, ldx, rows, n_vec, R, true);
   API_END(c)
+}
+
+int chfsi_overlap(chfsi_ctx* c, const void* X, int64_t ldx, const void* Y, int64_t ldy, int n_vec, double* S_h) {
+  if (!c) return CHFSI_EINVAL;
+  API_BEGIN(c)
+  check_block(c, X, ldx, n_vec, "X");
+  check_block(c, Y, ldy, n_vec, "Y");
+  CHFSI_CHECK(S_h != nullptr, CHFSI_EINVAL, "S_h is NULL");
+  std::vector<cplx> S;
+  gram(c, (const double2*)X, ldx, (const double2*)Y, ldy, 2 * c->n_nodes, n_vec, S, false);
+  std::memcpy(S_h, S.data(), S.size() * sizeof(cplx));
+  API_END(c)
+}
+
+size_t chfsi_workspace_bytes(const chfsi_ctx* c, int ik, int n_vec, int op) {
+  if (!c || n_vec < 1 || ik < 0 || ik >= (int)c->kp.size()) return 0;
+  auto cdiv = [](int64_t a, int64_t b) { return (int)((a + b - 1) / b); };
+  const size_t n = (size_t)n_vec;
+  const int64_t rows = 2 * c->n_nodes;
+  // gram(): partial tiles of one resident round + the reduced matrix + tile list
+  const int nti = cdiv(n_vec, 128), ntj = cdiv(n_vec, 64);
+  const size_t ntl = (size_t)nti * ntj;
+  const int64_t n_chunks = std::max<int64_t>(1, (rows + 255) / 256);
+  const size_t n_groups = (size_t)std::max<int64_t>(1, std::min<int64_t>(n_chunks, 512 / (int64_t)ntl));
+  const size_t gram_b = (2 * (n_groups * n * n + n * n) + ntl) * sizeof(double);
+  // rotate_inplace(): a row panel of at most 128 MiB + the n x n rotation
+  int64_t prow = std::max<int64_t>(128, ((int64_t)1 << 27) / ((int64_t)n * 16));
+  prow = std::min<int64_t>(prow, rows);
+  prow = (prow + 127) / 128 * 128;
+  const size_t rot_b = ((size_t)prow * n + n * n) * sizeof(double2);
+  const size_t resid_b = (256 * n + n) * sizeof(double);
+  const size_t nl_b = nonlocal_scratch_bytes(*c->kp[ik], n_vec);
+  switch (op) {
+    case CHFSI_OP_APPLY:
+    case CHFSI_OP_FILTER:
+      return nl_b;
+    case CHFSI_OP_CHOL_GS:
+      return gram_b + rot_b;
+    case CHFSI_OP_RAYLEIGH_RITZ:
+      return std::max(std::max(nl_b, gram_b), resid_b) + rot_b;
+    case CHFSI_OP_DENSITY: {
+      const int cols = c->nq == c->np1 ? 4 : 1;
+      const int64_t groups = std::min<int64_t>(std::max(1, cdiv(n_vec, cols)),
+                                               std::max(1, cdiv(4096, std::max(1, c->n_cells))));
+      return (size_t)groups * c->n_cells * c->nq3 * 4 * sizeof(double) + n * sizeof(double);
+    }
+    default:
+      return 0;
+  }
 }
 
 int chfsi_rayleigh_ritz(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,

@@ -318,3 +318,53 @@ def test_cheb_filter_residual_form():
         ratios.append(out["mixed"] / out["mixed_plain"])
     assert ratios[-1] < 0.5 * ratios[0]          # the advantage grows with convergence
     op.close()
+
+
+def test_cholgs_badly_scaled_columns_and_overlap():
+    """CholGS on a block whose column norms span 12 orders of magnitude (the
+    diagonal pre-scaling keeps the factor well conditioned): X^H X = I to 1e-13
+    through chfsi_overlap, and the span equals the oracle's CholGS span.  The
+    overlap itself is the plain definition X^H Y."""
+    s = SYSTEMS["tiny"]()
+    op = _op(s)
+    X0 = synth.start_block(s, s.n_dof)
+    scale = 10.0 ** np.linspace(-6, 6, s.n_vec)
+    Xs = X0 * scale[None, :]
+    Y0 = synth.random_block(9, s.n_dof, s.n_vec)
+    S = op.overlap(torch.tensor(Xs, device="cuda"), torch.tensor(Y0, device="cuda"))
+    ref = Xs.conj().T @ Y0
+    assert np.abs(S - ref).max() <= 1e-13 * np.abs(ref).max()
+    X = torch.tensor(Xs, device="cuda")
+    op.chol_gs(X)
+    G = op.overlap(X, X)
+    orth = np.abs(G - np.eye(s.n_vec)).max()
+    Xo = och.chol_gs(Xs)
+    span = och.sin_largest_angle(X.cpu().numpy(), Xo)
+    _say(f"[cholgs scaled] ||X^H X - I||_max {orth:.2e}, sin(angle) to the oracle span {span:.2e}")
+    assert orth < 1e-13 and span < 1e-10
+    op.close()
+
+
+def test_workspace_bytes_bound_the_library_allocations():
+    """chfsi_workspace_bytes covers what a fresh context allocates for a filter,
+    CholGS and Rayleigh-Ritz (device memory measured before and after; the
+    allocator's page rounding is allowed for)."""
+    s = SYSTEMS["k_l2_aniso"]()
+    op = _op(s)
+    X = torch.tensor(synth.start_block(s, s.n_dof), device="cuda")
+    W = torch.empty_like(X)
+    torch.cuda.synchronize()
+    ws = {k: op.workspace_bytes(s.n_vec, k) for k in ("apply", "filter", "chol_gs", "rayleigh_ritz", "density")}
+    _say(f"[workspace] {ws}")
+    assert all(v > 0 for v in ws.values())
+    assert ws["filter"] == ws["apply"] and ws["rayleigh_ritz"] >= ws["filter"]
+    free0 = torch.cuda.mem_get_info()[0]
+    op.cheb_filter(X, W, 4, 5.0, 40.0, -2.0)
+    op.chol_gs(X)
+    op.rayleigh_ritz(X, W)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    bound = ws["filter"] + ws["chol_gs"] + ws["rayleigh_ritz"] + (8 << 20)
+    _say(f"[workspace] measured {used} B, bound {bound} B")
+    assert used <= bound
+    op.close()
