@@ -902,6 +902,155 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
   }
 }
 
+// Densities (one operand, two spins) with n_q = n_p: a workgroup of 512 threads
+// owns one cell and a group of columns and walks it in chunks of DC = 8 columns,
+// each chunk in two rounds (spin up, then spin down) of 8 LDS fields of n_p^3
+// values (44 KB at n_p = 7).  A round's z-line loads cover 8 consecutive
+// columns of one row, i.e. whole 128-byte lines, so a line is fetched once per
+// cell that holds the node; after the spin-up round each thread keeps the 8
+// spin-up values of its quadrature point in registers and combines them with
+// the spin-down round.  The next round's z-lines are loaded while the current
+// one runs its LDS phases.  Output as qfield_sf_kernel (wJ = 0: no weights).
+constexpr int kDenCols = 8;
+
+template <int NP>
+__global__ __launch_bounds__(kQfThreads) void density_sf_kernel(
+    const double2* __restrict__ X, int64_t ldx, int n_vec, const int32_t* __restrict__ cell_nodes,
+    const double* __restrict__ minv_sqrt, const double* __restrict__ tab, int n_cells, int n_groups,
+    int cols_per_group, const double* __restrict__ colw, double* __restrict__ partial) {
+  constexpr int NT = kQfThreads, DC = kDenCols;
+  constexpr int N2 = NP * NP, N3 = N2 * NP;
+  constexpr int NTASK = DC * N2, TPT = (NTASK + NT - 1) / NT;
+  constexpr int QPT = (N3 + NT - 1) / NT;
+  extern __shared__ double2 den_sm[];
+  double2* buf = den_sm;                // [DC][N3]
+  const double* eoBf = tab + 2 * N2 + NP;
+  const int total = n_cells * n_groups;
+  const int per_xcd = (total + 7) / 8;
+  const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (bid >= total) return;
+  const int e = bid % n_cells, g = bid / n_cells, tid = threadIdx.x;
+  const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
+  const int32_t* nodes = cell_nodes + (size_t)e * N3;
+
+  // the thread's z-line tasks (column offset c fastest, then the line l)
+  int32_t nd[TPT][NP];
+  double sc[TPT][NP];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int t = min(tid + NT * k, NTASK - 1);
+    const int l = t / DC;
+#pragma unroll
+    for (int z = 0; z < NP; ++z) {
+      nd[k][z] = nodes[l + z * N2];
+      sc[k][z] = minv_sqrt[nd[k][z]];
+    }
+  }
+  auto zload = [&](int n0, int sp, double2 (&zv)[TPT][NP]) {
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int t = min(tid + NT * k, NTASK - 1);
+      const int col = min(n0 + t % DC, c_end - 1);
+#pragma unroll
+      for (int z = 0; z < NP; ++z) zv[k][z] = X[(2 * (int64_t)nd[k][z] + sp) * ldx + col];
+    }
+  };
+  double2 zv[TPT][NP];
+  zload(c_begin, 0, zv);
+  double acc[QPT][4];
+  double2 up[QPT][DC];
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
+  for (int n0 = c_begin; n0 < c_end; n0 += DC) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      // z interpolation in registers (zero past the last column) into LDS
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) {
+        const int t = tid + NT * k;
+        if (t >= NTASK) break;
+        const int c = t % DC, l = t / DC;
+        const bool ok = n0 + c < c_end;
+        double2 u[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          const double f = ok ? sc[k][i] : 0.0;
+          u[i] = double2{f * zv[k][i].x, f * zv[k][i].y};
+        }
+        double2* out = buf + c * N3 + l;
+        double2 r[NP];
+        sf_eo<double, NP, false>(eoBf, u, r);
+#pragma unroll
+        for (int o = 0; o < NP; ++o) out[o * N2] = r[o];
+      }
+      // the next round's rows: spin down of this chunk, or spin up of the next
+      if (sp == 0) zload(n0, 1, zv);
+      else if (n0 + DC < c_end) zload(n0 + DC, 0, zv);
+      lds_barrier();
+      sf_line_pass<NP, DC, 1, NT>(eoBf, buf, buf);
+      lds_barrier();
+      sf_line_pass<NP, DC, 0, NT>(eoBf, buf, buf);
+      lds_barrier();
+#pragma unroll
+      for (int j = 0; j < QPT; ++j) {
+        const int q = tid + NT * j;
+        if (q >= N3) continue;
+        if (sp == 0) {
+#pragma unroll
+          for (int c = 0; c < DC; ++c) up[j][c] = buf[c * N3 + q];
+        } else {
+#pragma unroll
+          for (int c = 0; c < DC; ++c) {
+            const double cw = (n0 + c < c_end) ? (colw ? colw[n0 + c] : 1.0) : 0.0;
+            const double2 u0 = up[j][c], u1 = buf[c * N3 + q];
+            const double r00 = u0.x * u0.x + u0.y * u0.y;
+            const double r11 = u1.x * u1.x + u1.y * u1.y;
+            const double r01 = u0.x * u1.x + u0.y * u1.y, i01 = u0.x * u1.y - u0.y * u1.x;
+            acc[j][0] += cw * (r00 + r11);
+            acc[j][1] += cw * (2.0 * r01);       // u^H sigma_x u
+            acc[j][2] += cw * (2.0 * i01);       // u^H sigma_y u
+            acc[j][3] += cw * (r00 - r11);       // u^H sigma_z u
+          }
+        }
+      }
+      lds_barrier();   // the next round overwrites the buffer
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) {
+    const int q = tid + NT * j;
+    if (q >= N3) continue;
+    double* out = partial + (((size_t)g * n_cells + e) * N3 + q) * 4;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) out[d] = acc[j][d];
+  }
+}
+
+template <int NP>
+static void launch_density_sf(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* colw,
+                              double* rho, double* mag) {
+  constexpr int DC = kDenCols;
+  const size_t sh = (size_t)DC * NP * NP * NP * sizeof(double2);
+  if (c->mf_tab.n == 0) mf_prepare(c);
+  const int max_groups = std::max(1, cdiv(n_vec, DC));
+  const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
+  int groups = std::min(max_groups, want);
+  const int cpg = DC * cdiv(cdiv(n_vec, groups), DC);
+  groups = cdiv(n_vec, cpg);
+  const int64_t n_points = (int64_t)c->n_cells * c->nq3;
+  c->cd_partial.alloc((size_t)groups * n_points * 4);
+  const int64_t total = (int64_t)c->n_cells * groups;
+  CHFSI_CHECK(total < (int64_t)1 << 30, CHFSI_EINVAL, "densities: too many work items");
+  StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, (double)c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
+  hipLaunchKernelGGL((density_sf_kernel<NP>), dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kQfThreads), sh,
+                     c->stream, X, ldx, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->mf_tab.ptr, c->n_cells,
+                     groups, cpg, colw, c->cd_partial.ptr);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
+                     dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, 1.0, rho, mag);
+  LAUNCH_CHECK();
+}
+
 template <int NP, int NS>
 static void launch_qfield_sf(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y, int64_t ldy,
                              int n_vec, const double* colw, int wJ, double alpha, double* dV, double* dB) {
@@ -988,6 +1137,19 @@ void cross_density(chfsi_ctx* c, const double2* L, int64_t ldl, const double2* Y
 
 void densities(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* occ_d, double* rho,
                double* mag) {
+  if (c->nq == c->np1) {
+    switch (c->np1) {
+      case 2: launch_density_sf<2>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 3: launch_density_sf<3>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 4: launch_density_sf<4>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 5: launch_density_sf<5>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 6: launch_density_sf<6>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 7: launch_density_sf<7>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 8: launch_density_sf<8>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      case 9: launch_density_sf<9>(c, X, ldx, n_vec, occ_d, rho, mag); return;
+      default: break;
+    }
+  }
   launch_cross_density<2>(c, X, ldx, X, ldx, n_vec, occ_d, 0, 1.0, rho, mag);
 }
 
