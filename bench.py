@@ -9,17 +9,25 @@ V_eff, noncollinear B_xc, 64 pseudo-atoms with l <= 2 spin-orbit projectors,
 N = 512 vectors filtered in 4 blocks of 128, Chebyshev degree 24, Gamma point.
 
 Printed JSON (one line, rank 0):
-  value        FP64 filter throughput, TFLOP/s, algorithmic count (a complex
-               multiply-add = 8 flops) over the filter sections of the timed passes
+  value        FP64 filter throughput, TFLOP/s, in the 4M count of the dense complex
+               cell product (a complex multiply-add = 8 flops) over the filter sections
+               of the timed passes; filter_tflops_real_work counts the Pauli form's own
+               products (0.75 of the 4M cell count at Gamma)
   ms_per_step  wall time per FP64 pass (filter + CholGS + RR), the K timed passes
-  roofline     the FP64 cell-product kernel (dominant): algorithmic flops per
-               launch / mean launch time from HIP events, against 78.6 TFLOP/s
-  mixed        from the same FP64 prologue and warm-up, the timed passes with FP32
-               cell/projector products in applies 1..m-1: per-pass time, speedup and
-               the largest Ritz-value difference from the FP64 run
-  mixed_resid  the same with the residual form of the filter (every correction
-               product in FP32)
-  cpu_baseline the FP64 oracle on a bounded sample (see `sample`)
+  roofline     the FP64 cell-product kernel (dominant): the Pauli form's real flops per
+               launch / mean launch time from HIP events, against 78.6 TFLOP/s (the 4M
+               and issued-MFMA rates beside it), with the counter-measured HBM traffic
+  mixed, mixed_resid   the FP32 filter forms (plain: FP32 cell/projector products in
+               applies 1..m-1; residual form: every correction product in FP32), timed
+               from the same start over fewer passes; their Ritz values are compared
+               with the FP64 ones after the same number of passes (unconverged)
+  matrix_free  the same passes with the sum-factorised local operator (FP64 and both
+               FP32 forms) and its HBM roofline
+  eig_bar      every form taken to convergence on the reduced instance of the large
+               system: per-eigenvalue |dtheta| of the wanted pairs against FP64 (the
+               1e-7 Ha bar of the FP32 forms); fastest_pass_within_1e-7_Ha uses it
+  density      rho and m of the Ritz block with 500 K occupations
+  cpu_baseline the FP64 oracle timed on the host (see cpu_baseline())
 """
 from __future__ import annotations
 
@@ -302,7 +310,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=os.environ.get("CHFSI_BENCH_WORKLOAD", "scale"),
-                    help="scale (default), batch (k-grid + uneven systems) or adjoint")
+                    help="scale (default), batch (k-grid + uneven systems), adjoint, or kernels "
+                         "(a short run of every hot kernel on the large mesh, for profilers)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-matfree", action="store_true")
@@ -318,11 +327,68 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         out = bench_batch(args, torch)
+    elif args.workload == "kernels":
+        out = bench_kernels(args, torch)
     elif args.workload == "adjoint":
         out = bench_adjoint(args, torch)
     else:
         out = bench_scale(args, torch)
     print(json.dumps(out), flush=True)
+
+
+def bench_kernels(args, torch):
+    """A short run of every hot kernel on the large mesh, for counter and trace
+    profiling: per operator form (matrix-free, then cell matrices), a Lanczos
+    bound, CholGS + Rayleigh-Ritz on all 512 columns, one degree-4 filter of a
+    128-column block in FP64 and in mixed precision, CholGS + Rayleigh-Ritz again;
+    then the densities of the block."""
+    import synth
+    from paper_2410_02754_amd import fermi_dirac
+    s = synth.config("scale")
+    t0 = time.perf_counter()
+    op = build_operator(s, torch, form="matrix_free")
+    X = torch.empty((s.n_dof, s.n_vec), dtype=torch.complex128, device="cuda")
+    W = torch.empty_like(X)
+    Wf = torch.empty((s.n_dof, s.block), dtype=torch.complex128, device="cuda")
+    v0 = torch.empty((s.n_dof, 1), dtype=torch.complex128, device="cuda")
+    times = {}
+    for form in ("matrix_free", "cell"):
+        if form != op.form:
+            import synth as sy
+            pts = op.quad_points().reshape(-1, 3)
+            V = torch.tensor(sy.veff(s, pts).reshape(op.n_cells, op.nq3), device="cuda")
+            B = torch.tensor(sy.bxc(s, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+            op.set_form(form)
+            op.set_local(V, B)
+            del V, B
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        op.fill_random(X, s.seed, n_total_cols=s.n_vec)
+        op.fill_random(v0, s.seed + 1)
+        _, hi = op.lanczos_bounds(v0[:, 0], 10)
+        op.chol_gs(X)
+        theta, _ = op.rayleigh_ritz(X, W)
+        for prec in ("fp64", "mixed"):
+            op.cheb_filter(X[:, :s.block], Wf, 4, float(theta[-1]), hi, float(theta[0]), prec=prec)
+        op.chol_gs(X)
+        theta, _ = op.rayleigh_ritz(X, W)
+        torch.cuda.synchronize()
+        times[form] = time.perf_counter() - t
+        log(f"[bench] kernels {form}: {times[form]:.2f} s")
+    f, _, _ = fermi_dirac(theta, 0.85 * s.n_vec, 500 * K_B_HA)
+    rho = torch.zeros((op.n_cells, op.nq3), dtype=torch.float64, device="cuda")
+    mag = torch.zeros((op.n_cells, op.nq3, 3), dtype=torch.float64, device="cuda")
+    op.density(X, f, rho, mag)
+    torch.cuda.synchronize()
+    op.close()
+    total = time.perf_counter() - t0
+    return {"metric": "kernel sample (profiling run)", "value": round(total, 3), "unit": "s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * total, 1), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "kernels: scale mesh (20^3 cells, p=6), both operator forms, one 128-column "
+                                   "degree-4 filter per precision, CholGS + RR on 512 columns, densities",
+                       "parallelism": "single GPU"},
+            "seconds_by_form": {k: round(v, 3) for k, v in times.items()}}
 
 
 def bench_density(op, s, X, theta, torch, reps=3):
