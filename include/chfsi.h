@@ -23,7 +23,8 @@
  *    internal scratch) and frees it in chfsi_destroy.
  *  - Multivector layout: row-major [2M][ld] complex numbers, interleaved
  *    (re, im).  Row r = 2 I + alpha is node I, spin alpha (eqn:GHEP); the n_vec
- *    columns of a row are contiguous.  ld >= n_vec.  complex128 everywhere
+ *    columns of a row are contiguous.  n_vec >= 1 (an empty block is
+ *    CHFSI_EINVAL) and ld >= n_vec; pointers 16-byte aligned.  complex128 everywhere
  *    (mixed precision converts internally).  A block of a wider array is
  *    passed as (pointer to its first column, n_vec, ld of the wide array).
  *  - Streams: all device work is enqueued on the HIP stream given to

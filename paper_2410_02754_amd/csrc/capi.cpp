@@ -607,6 +607,12 @@ int chfsi_fermi_dirac(int n, const double* eps, const double* w, double n_electr
   } catch (const chfsi::Error& e) {
     g_create_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return CHFSI_EINVAL;
   }
   return CHFSI_OK;
 }

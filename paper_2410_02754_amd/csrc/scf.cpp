@@ -60,6 +60,12 @@ int chfsi_field_inner(chfsi_ctx* c, const double* r1, const double* m1, const do
   } catch (const Error& e) {
     c->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    c->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   return CHFSI_OK;
 }
@@ -74,6 +80,12 @@ int chfsi_hartree(chfsi_ctx* c, const double* rho, double* vh, double tol, int m
   } catch (const Error& e) {
     c->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    c->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   return CHFSI_OK;
 }
@@ -98,6 +110,12 @@ int chfsi_kerker(chfsi_ctx* c, double k0, const double* f, double* out, double t
   } catch (const Error& e) {
     c->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    c->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   return CHFSI_OK;
 }
@@ -110,6 +128,12 @@ int chfsi_exchange(chfsi_ctx* c, const double* rho, const double* m, double* vx,
   } catch (const Error& e) {
     c->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    c->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   return CHFSI_OK;
 }
@@ -132,6 +156,12 @@ int chfsi_interpolate_block(chfsi_ctx* cc, chfsi_ctx* cf, const void* Yc, int64_
   } catch (const Error& e) {
     cf->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    cf->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    cf->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   return CHFSI_OK;
 }
@@ -251,11 +281,13 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
         check_rc(chfsi_density(g, Xg, ldg, N, occ.data(), ro.ptr, mo.ptr), g, "scf_run: densities");
         // hold exactly N_e electrons under the cell quadrature
         const double q = P.n_electrons / field_integral(c, ro.ptr);
+        CHFSI_CHECK(std::isfinite(q) && q > 0.0, CHFSI_ENONFINITE, "scf_run: output density has no positive charge");
         field_axpby(c, np, q, ro.ptr, 0.0, nullptr, ro.ptr);
         field_axpby(c, 3 * np, q, mo.ptr, 0.0, nullptr, mo.ptr);
         field_axpby(c, np, 1.0, ro.ptr, -1.0, rho, fr.ptr);
         field_axpby(c, 3 * np, 1.0, mo.ptr, -1.0, mag, fm.ptr);
         const double nres = std::sqrt(field_inner(c, fr.ptr, fm.ptr, fr.ptr, fm.ptr));
+        CHFSI_CHECK(std::isfinite(nres), CHFSI_ENONFINITE, "scf_run: non-finite density residual");
         double eband = 0.0;
         for (int n = 0; n < N; ++n) eband += occ[n] * theta[n];
         if (hist && nh < max_hist)
@@ -310,6 +342,12 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
   } catch (const Error& e) {
     fine->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    fine->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    fine->last_error = e.what();
+    return CHFSI_EINVAL;
   }
 }
 

@@ -75,6 +75,12 @@ int chfsi_stats_read(chfsi_ctx* c, chfsi_stage_stats* out) {
   } catch (const Error& e) {
     c->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    c->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   for (int i = 0; i < CHFSI_N_STAGES; ++i) out[i] = c->stats[i];
   return CHFSI_OK;
@@ -87,6 +93,12 @@ int chfsi_stats_reset(chfsi_ctx* c) {
   } catch (const Error& e) {
     c->last_error = e.msg;
     return e.code;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return CHFSI_ENOMEM;
+  } catch (const std::exception& e) {
+    c->last_error = e.what();
+    return CHFSI_EINVAL;
   }
   for (int i = 0; i < CHFSI_N_STAGES; ++i) c->stats[i] = chfsi_stage_stats{};
   return CHFSI_OK;

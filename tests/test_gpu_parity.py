@@ -277,6 +277,32 @@ def test_error_paths():
     op.close()
 
 
+def test_empty_blocks_are_rejected():
+    """A block of zero columns is an argument error (CHFSI_EINVAL) at every call that
+    takes one, and leaves the other operands untouched."""
+    from paper_2410_02754_amd import ChfsiError
+    s = SYSTEMS["gl_p2_nq4"]()
+    op = _op(s)
+    E = torch.empty((s.n_dof, 0), dtype=torch.complex128, device="cuda")
+    W = torch.ones((s.n_dof, 4), dtype=torch.complex128, device="cuda")
+    rho = torch.zeros((op.n_cells, op.nq3), dtype=torch.float64, device="cuda")
+    mag = torch.zeros((op.n_cells, op.nq3, 3), dtype=torch.float64, device="cuda")
+    calls = {
+        "apply_H": lambda: op.apply_H(E, E),
+        "cheb_filter": lambda: op.cheb_filter(E, W, 3, 1.0, 2.0, 0.0),
+        "chol_gs": lambda: op.chol_gs(E),
+        "rayleigh_ritz": lambda: op.rayleigh_ritz(E, W),
+        "density": lambda: op.density(E, np.zeros(0), rho, mag),
+    }
+    for name, call in calls.items():
+        with pytest.raises(ChfsiError) as ei:
+            call()
+        assert ei.value.code == -1, name
+    torch.cuda.synchronize()
+    assert bool((W == 1).all()) and float(rho.abs().max()) == 0.0 and float(mag.abs().max()) == 0.0
+    op.close()
+
+
 def test_cheb_filter_residual_form():
     """The residual form Y = X p(Theta) + Z equals the plain filter (FP64), and
     with FP32 products its error shrinks with the residuals (the correction Z
