@@ -39,6 +39,13 @@ build leaves out; these stand-ins keep its structure):
   Rayleigh-Ritz on the first iteration of each grid, then `passes_first` passes on
   the first iteration and `passes` on the later ones, bounds from the previous
   Rayleigh-Ritz.  The Anderson history is cleared when the grid changes.
+* Brillouin-zone sampling (Sec. II.C: the sum over states becomes the sum over n
+  of the zone average over k): every k-point of the system carries its own block
+  and ChFSI passes, with weights w_k summing to one (equal by default); the
+  occupations f_nk are Fermi-Dirac numbers with one Fermi level for all (n, k),
+  fixed by sum_k w_k sum_n f_nk = N_e, and the densities are
+  rho = sum_k w_k sum_n f_nk |u_nk|^2 (likewise m) of the periodic parts u.  The
+  start block of k-point ik is the seeded block of seed + 7919 ik.
 """
 from __future__ import annotations
 
@@ -191,37 +198,75 @@ class Grid:
         self.atoms = atoms
         self.MD = self.mesh.lumped_mass()
 
-    def operator(self, V, B):
-        k = self.s.kpts[0]
+    def operator(self, V, B, ik=0):
+        k = self.s.kpts[ik]
         Hloc = ham.assemble_local(self.mesh, V, B, k)
         projs = ham.spinor_projectors(self.mesh, self.atoms, k, self.s.box)
         return ham.Operator(Hloc, projs, self.MD)
 
 
+KSEED = 7919      # start block of k-point ik: the seeded block of seed + KSEED ik
+
+
+def k_weights(system, kweights=None):
+    """The zone-average weights of the system's k-points (equal by default; given
+    weights must be >= 0 and sum to one)."""
+    nk = len(system.kpts)
+    if kweights is None:
+        return np.full(nk, 1.0 / nk)
+    w = np.asarray(kweights, dtype=np.float64).reshape(-1)
+    if w.shape[0] != nk or (w < 0).any() or abs(w.sum() - 1.0) > 1e-12:
+        raise ValueError("need one weight >= 0 per k-point, summing to one")
+    return w
+
+
+def occupations(thetas, w, n_electrons, kT):
+    """f_nk (list per k), mu: one Fermi level for all (n, k) with weights w_k."""
+    eps = np.concatenate([np.asarray(t, dtype=np.float64) for t in thetas])
+    wts = np.concatenate([np.full(len(t), wk) for t, wk in zip(thetas, w)])
+    f, mu, _ = oden.fermi_dirac(eps, n_electrons, kT, weights=wts)
+    out, i0 = [], 0
+    for t in thetas:
+        out.append(f[i0:i0 + len(t)])
+        i0 += len(t)
+    return out, mu
+
+
 def scf(fine_system, vext, bext, rho0, m0, n_electrons, kT, *, coarse_system=None, n_vec=None, degree=None,
         passes_first=4, passes=1, depth=4, alpha=0.5, k0=0.0, tol=1e-8, tol_coarse=1e-3, max_iter=40,
-        max_coarse=20, seed=0, lanczos_steps=40, X0=None):
+        max_coarse=20, seed=0, lanczos_steps=40, X0=None, kweights=None):
     """Run the SCF loop.  vext [E][nq^3], bext [E][nq^3][3] at the (shared)
-    quadrature points; rho0, m0 the initial input densities.  Returns a dict with
-    the history [(degree p of the grid, residual norm, mu, sum f theta, theta_0, upper bound
-    b of the filter)], the final
-    input and output densities, theta and X."""
+    quadrature points; rho0, m0 the initial input densities; every k-point of the
+    system is sampled with the weights kweights (equal by default); X0 an optional
+    start block (one array, or one per k-point).  Returns a dict with the history
+    [(degree p of the grid, residual norm, mu, sum_k w_k sum_n f_nk theta_nk,
+    lowest theta over k, upper bound b of the filter at the first k-point, the
+    bounds of all k-points)], the final input and output densities, and theta, X,
+    occ of the first k-point (theta_k, X_k, occ_k: all k-points)."""
     import synth
     grids = ([Grid(coarse_system, coarse_system.atoms)] if coarse_system is not None else []) + \
         [Grid(fine_system, fine_system.atoms)]
+    nk = len(fine_system.kpts)
+    if coarse_system is not None:
+        assert np.array_equal(np.asarray(coarse_system.kpts), np.asarray(fine_system.kpts))
+    w = k_weights(fine_system, kweights)
     n_vec = fine_system.n_vec if n_vec is None else n_vec
     degree = fine_system.degree if degree is None else degree
     rho_in, m_in = rho0.copy(), m0.copy()
     hist, xs, fs = [], [], []
     X = None
-    theta = None
+    theta = [None] * nk
     it = 0
     for gi, g in enumerate(grids):
         last = gi == len(grids) - 1
         if X is None:
-            X = synth.random_block(seed, g.s.n_dof, n_vec) if X0 is None else X0.copy()
+            if X0 is None:
+                X = [synth.random_block(seed + KSEED * ik, g.s.n_dof, n_vec) for ik in range(nk)]
+            else:
+                X = [np.array(x, copy=True) for x in (X0 if isinstance(X0, (list, tuple)) else [X0])]
+                assert len(X) == nk
         else:
-            X = interpolate_block(grids[gi - 1].mesh, g.mesh, X)
+            X = [interpolate_block(grids[gi - 1].mesh, g.mesh, x) for x in X]
         xs, fs = [], []
         first = True
         n_here = 0
@@ -229,27 +274,36 @@ def scf(fine_system, vext, bext, rho0, m0, n_electrons, kT, *, coarse_system=Non
             it += 1
             n_here += 1
             V, B = potentials(g.mesh, rho_in, m_in, vext, bext)
-            H = g.operator(V, B)
-            _, b = och.lanczos_bounds(H, synth.lanczos_start(g.s, g.s.n_dof), lanczos_steps)
-            if first:
-                X = och.chol_gs(X)
-                theta, X, _ = och.rayleigh_ritz(H, X)
-            for _ in range(passes_first if (first and gi == 0) else passes):
-                X = och.cheb_filter(H, X, degree, float(theta[-1]), b, float(theta[0]))
-                X = och.chol_gs(X)
-                theta, X, r = och.rayleigh_ritz(H, X)
+            bs = []
+            for ik in range(nk):
+                H = g.operator(V, B, ik)
+                _, b = och.lanczos_bounds(H, synth.lanczos_start(g.s, g.s.n_dof), lanczos_steps)
+                bs.append(b)
+                if first:
+                    X[ik] = och.chol_gs(X[ik])
+                    theta[ik], X[ik], _ = och.rayleigh_ritz(H, X[ik])
+                for _ in range(passes_first if (first and gi == 0) else passes):
+                    X[ik] = och.cheb_filter(H, X[ik], degree, float(theta[ik][-1]), b, float(theta[ik][0]))
+                    X[ik] = och.chol_gs(X[ik])
+                    theta[ik], X[ik], r = och.rayleigh_ritz(H, X[ik])
             first = False
-            f, mu, _ = oden.fermi_dirac(theta, n_electrons, kT)
-            rho_out, m_out = oden.density_magnetisation(g.mesh, g.MD, X, f)
+            f, mu = occupations(theta, w, n_electrons, kT)
+            rho_out, m_out = 0.0, 0.0
+            for ik in range(nk):
+                r_k, m_k = oden.density_magnetisation(g.mesh, g.MD, X[ik], w[ik] * f[ik])
+                rho_out, m_out = rho_out + r_k, m_out + m_k
             q = n_electrons / integrate(g.mesh, rho_out)
             rho_out, m_out = q * rho_out, q * m_out
             fr, fm = rho_out - rho_in, m_out - m_in
             nres = float(np.sqrt(inner(g.mesh, fr, fm, fr, fm)))
-            hist.append((g.s.p, nres, mu, float(np.dot(f, theta)), float(theta[0]), b))
+            eband = float(sum(w[ik] * np.dot(f[ik], theta[ik]) for ik in range(nk)))
+            th0 = float(min(t[0] for t in theta))
+            hist.append((g.s.p, nres, mu, eband, th0, bs[0], tuple(bs)))
             conv = nres < (tol if last else tol_coarse)
             if last and (conv or it >= max_iter):
                 return {"history": hist, "rho_in": rho_in, "m_in": m_in, "rho_out": rho_out, "m_out": m_out,
-                        "theta": theta, "X": X, "occ": f, "converged": conv}
+                        "theta": theta[0], "X": X[0], "occ": f[0], "theta_k": np.array(theta), "X_k": X,
+                        "occ_k": np.array(f), "converged": conv}
             xs.append((rho_in, m_in))
             fs.append((fr, fm))
             xs, fs = xs[-depth:], fs[-depth:]

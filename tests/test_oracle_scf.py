@@ -233,3 +233,106 @@ def test_scf_two_grid_with_atoms_converges_to_a_fixed_point():
     assert math.sqrt(scf.inner(mesh, fr, fm, fr, fm)) < 1e-7
     # |m| <= rho pointwise
     assert np.all(np.linalg.norm(out["m_out"], axis=-1) <= out["rho_out"] * (1 + 1e-12))
+
+
+# ---------------------------------------------------------------- Brillouin-zone sampling
+def _kpt_system(kpts, seed=3, b_mag=None):
+    """Two SOC pseudo-atoms (l <= 1) in a 2^3-cell box, p = 2: small enough for a
+    dense diagonalisation per k-point."""
+    kw = dict(n_cells=(2, 2, 2), box=(4.5, 4.5, 4.5), p=2, n_q=4, n_atoms=2, lmax=1, rcut_sigmas=5.0,
+              n_vec=8, degree=8, seed=seed, kpts=kpts)
+    if b_mag is not None:
+        kw["b_mag"] = b_mag
+    s = synth.make_system("kscf", **kw)
+    mesh = ham.mesh_for(s)
+    pts = mesh.all_quad_points().reshape(-1, 3)
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    return s, mesh, synth.veff(s, pts).reshape(E, nq3), synth.bxc(s, pts).reshape(E, nq3, 3)
+
+
+def test_scf_duplicated_kpoint_equals_the_single_kpoint():
+    """The same k-point listed twice with weights 1/2, 1/2 (and the same start
+    block) is the single k-point: history and densities agree to rounding."""
+    k = (0.0, 0.0, 0.35)
+    s1, mesh, vext, bext = _kpt_system([k])
+    s2, _, _, _ = _kpt_system([k, k])
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    n_e = 3.0
+    rho0 = np.full((E, nq3), n_e / 4.5 ** 3)
+    m0 = 0.1 * rho0[..., None] * np.array([0.0, 0.6, 0.8])
+    X0 = synth.random_block(0, s1.n_dof, 8)
+    kw = dict(passes_first=5, passes=2, depth=4, alpha=0.5, k0=0.6, tol=1e-8, max_iter=6)
+    a = scf.scf(s1, vext, bext, rho0, m0, n_e, 1e-3, X0=X0, **kw)
+    b = scf.scf(s2, vext, bext, rho0, m0, n_e, 1e-3, X0=[X0, X0], kweights=[0.5, 0.5], **kw)
+    assert len(a["history"]) == len(b["history"])
+    for ha, hb in zip(a["history"], b["history"]):
+        for i in range(1, 6):
+            assert abs(ha[i] - hb[i]) <= 1e-11 * max(1.0, abs(ha[i])), (i, ha[i], hb[i])
+    for key in ("rho_out", "m_out", "rho_in", "m_in"):
+        assert np.abs(a[key] - b[key]).max() <= 1e-12 * np.abs(a[key]).max()
+    assert np.abs(b["occ_k"][0] - b["occ_k"][1]).max() == 0.0
+
+
+def test_scf_time_reversed_pair_cancels_the_magnetisation():
+    """No external field, no input magnetisation, spin-orbit atoms: the pair
+    {k, -k} with equal weights gives m = 0 (Kramers partners u_{-k} = i sigma_y
+    conj(u_k) carry opposite spin densities) and the charge density of k alone,
+    while k alone leaves a spin-orbit magnetisation."""
+    k = np.array([0.0, 0.3, 0.45])
+    s1, mesh, vext, _ = _kpt_system([tuple(k)])
+    s2, _, _, _ = _kpt_system([tuple(k), tuple(-k)])
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    bext = np.zeros((E, nq3, 3))
+    n_e = 3.0
+    rho0 = np.full((E, nq3), n_e / 4.5 ** 3)
+    m0 = np.zeros((E, nq3, 3))
+    kw = dict(passes_first=10, passes=2, depth=3, alpha=0.5, k0=0.6, tol=1e-12, max_iter=1)
+    one = scf.scf(s1, vext, bext, rho0, m0, n_e, 1e-3, **kw)
+    pair = scf.scf(s2, vext, bext, rho0, m0, n_e, 1e-3, **kw)
+    rmax = np.abs(pair["rho_out"]).max()
+    m_one = np.abs(one["m_out"]).max() / rmax
+    m_pair = np.abs(pair["m_out"]).max() / rmax
+    d_rho = np.abs(pair["rho_out"] - one["rho_out"]).max() / rmax
+    print(f"[scf k,-k] |m|/rho: k alone {m_one:.1e}, pair {m_pair:.1e}; rho difference {d_rho:.1e}")
+    assert m_one > 1e-4
+    assert m_pair < 1e-9 and d_rho < 1e-9
+    occd = pair["occ_k"][0] > 1e-12          # the top of the block is not converged
+    assert np.abs(pair["theta_k"][0] - pair["theta_k"][1])[occd].max() < 1e-9
+
+
+def test_scf_one_iteration_is_the_dense_zone_average():
+    """One map evaluation with two k-points of unequal weight against its plain
+    definition: dense eigenpairs of each H^k, one Fermi level for all (n, k) with
+    sum_k w_k sum_n f_nk = N_e, rho = sum_k w_k sum_n f_nk |u_nk|^2 (and m), scaled
+    to N_e under the cell quadrature."""
+    from oracle import density as oden
+    kpts = [(0.0, 0.0, 0.7), (0.25, 0.0, -0.35)]
+    s, mesh, vext, bext = _kpt_system(kpts, seed=5)
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    n_e, kT, w = 3.0, 2e-3, np.array([0.3, 0.7])
+    rho0 = np.full((E, nq3), n_e / 4.5 ** 3)
+    m0 = 0.05 * rho0[..., None] * np.array([0.6, 0.0, 0.8])
+    out = scf.scf(s, vext, bext, rho0, m0, n_e, kT, passes_first=12, max_iter=1, tol=1e-14, kweights=w)
+    V, B = scf.potentials(mesh, rho0, m0, vext, bext)
+    g = scf.Grid(s, s.atoms)
+    th, vec = [], []
+    for ik in range(2):
+        ev, U = np.linalg.eigh(g.operator(V, B, ik).toarray())
+        th.append(ev[:8])
+        vec.append(U[:, :8])
+    eps = np.concatenate(th)
+    f, mu, _ = oden.fermi_dirac(eps, n_e, kT, weights=np.repeat(w, 8))
+    rho, m = 0.0, 0.0
+    for ik in range(2):
+        r_k, m_k = oden.density_magnetisation(mesh, g.MD, vec[ik], w[ik] * f[8 * ik:8 * ik + 8])
+        rho, m = rho + r_k, m + m_k
+    q = n_e / scf.integrate(mesh, rho)
+    rho, m = q * rho, q * m
+    occd = f.reshape(2, 8) > 1e-12               # the top of the block is not converged
+    d_th = np.abs(out["theta_k"] - np.array(th))[occd].max()
+    d_rho = np.abs(out["rho_out"] - rho).max() / np.abs(rho).max()
+    d_m = np.abs(out["m_out"] - m).max() / np.abs(rho).max()
+    print(f"[scf zone average] theta {d_th:.1e}, mu {abs(out['history'][0][2] - mu):.1e}, rho {d_rho:.1e}, m {d_m:.1e}")
+    assert d_th < 1e-10 and abs(out["history"][0][2] - mu) < 1e-10
+    assert d_rho < 1e-9 and d_m < 1e-9
+    assert abs(float(np.dot(w, [np.dot(f[8 * i:8 * i + 8], th[i]) for i in range(2)])) - out["history"][0][3]) < 1e-10
