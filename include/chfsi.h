@@ -372,19 +372,22 @@ typedef struct {
   uint64_t seed;        /* start block: SplitMix64 stream of chfsi_fill_random       */
   uint64_t lanczos_seed;/* Lanczos start vector stream                               */
   const double* bounds_h;/* host [n_bounds]: the filter's upper bound b of iteration i
-                          (a known bound of the spectrum; the Lanczos run is skipped),
-                          or NULL: b from lanczos_steps Lanczos steps every iteration */
+                          at k-point ik in entry i n_k + ik (a known bound of the
+                          spectrum; the Lanczos run is skipped), or NULL: b from
+                          lanczos_steps Lanczos steps every iteration            */
   int n_bounds;         /* entries of bounds_h (iterations past them use Lanczos)    */
+  const double* kweights_h;/* host [n_k]: zone-average weights of the context's k-points
+                          (>= 0, summing to 1), or NULL: equal weights           */
 } chfsi_scf_params;
 
 typedef struct {
   int p;                /* degree of the grid of this iteration                      */
   double resid;         /* || F(x) - x || in the norm of eqn:innerPdt                */
   double mu;            /* chemical potential, Ha                                    */
-  double band_energy;   /* sum_n f_n theta_n, Ha                                     */
-  double theta0;        /* lowest Ritz value, Ha                                     */
+  double band_energy;   /* sum_k w_k sum_n f_nk theta_nk, Ha                         */
+  double theta0;        /* lowest Ritz value over the k-points, Ha                   */
   int hartree_iters;    /* conjugate-gradient steps of this iteration's Hartree solve */
-  double b;             /* the filter's upper bound in this iteration, Ha            */
+  double b;             /* the filter's upper bound in this iteration (k-point 0), Ha */
 } chfsi_scf_record;
 
 /* The SCF loop.  Each iteration: V_eff = vext + V_H[rho] + V_x, B_xc = bext + B_x
@@ -399,12 +402,19 @@ typedef struct {
  * starts there, leaves it when the residual is below tol_coarse (or after
  * max_coarse iterations), moves the block with chfsi_interpolate_block and
  * clears the Anderson history; the densities carry over.  Both contexts need
- * their atoms set; k-point 0 is used.
+ * their atoms set.
+ * Brillouin-zone sampling (Sec. II.C): every k-point of the fine context (the
+ * coarse one must have the same k-points) carries its own block, Lanczos bound
+ * and ChFSI passes; the occupations f_nk have one Fermi level for all (n, k)
+ * with sum_k w_k sum_n f_nk = N_e (chfsi_fermi_dirac with weights w_k), and the
+ * output densities are sum_k w_k sum_n f_nk |u_nk|^2 (likewise m).  The start
+ * block of k-point ik is the chfsi_fill_random stream of seed + 7919 ik.
  * In/out: rho_d, m_d hold the initial input densities and, on return, the last
- * input; rho_out_d, m_out_d the last output; X_d [2M][ldx] (fine grid) the last
- * Ritz block; theta_h[n_vec], occ_h[n_vec] (host, may be NULL) its Ritz values and
- * occupations; hist_h[max_hist] one record per iteration, *n_hist the count;
- * *converged 1 if the fine-grid residual fell below tol within max_iter. */
+ * input; rho_out_d, m_out_d the last output; X_d (fine grid) the last Ritz
+ * blocks, block ik [2M][ldx] at X_d + ik 2M ldx complex entries; theta_h and
+ * occ_h [n_k][n_vec] (host, may be NULL) their Ritz values and occupations;
+ * hist_h[max_hist] one record per iteration, *n_hist the count; *converged 1 if
+ * the fine-grid residual fell below tol within max_iter. */
 int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* params, const double* vext_d,
                   const double* bext_d, double* rho_d, double* m_d, double* rho_out_d, double* m_out_d, void* X_d,
                   int64_t ldx, double* theta_h, double* occ_h, chfsi_scf_record* hist_h, int max_hist, int* n_hist,

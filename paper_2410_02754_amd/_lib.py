@@ -47,7 +47,8 @@ class ScfParams(C.Structure):
                 ("field_max_iter", C.c_int), ("prec_mode", C.c_int), ("n_electrons", C.c_double),
                 ("kT", C.c_double), ("alpha", C.c_double), ("k0", C.c_double), ("tol", C.c_double),
                 ("tol_coarse", C.c_double), ("field_tol", C.c_double), ("seed", C.c_uint64),
-                ("lanczos_seed", C.c_uint64), ("bounds_h", C.POINTER(C.c_double)), ("n_bounds", C.c_int)]
+                ("lanczos_seed", C.c_uint64), ("bounds_h", C.POINTER(C.c_double)), ("n_bounds", C.c_int),
+                ("kweights_h", C.POINTER(C.c_double))]
 
 
 class ScfRecord(C.Structure):

@@ -358,21 +358,31 @@ def interpolate_block(coarse: "Operator", fine: "Operator", Yc, Yf):
 
 SCF_DEFAULTS = dict(passes_first=4, passes=1, depth=4, max_iter=40, max_coarse=20, lanczos_steps=40,
                     field_max_iter=20000, prec="fp64", alpha=0.5, k0=0.0, tol=1e-8, tol_coarse=1e-3,
-                    field_tol=1e-13, seed=0, lanczos_seed=1, bounds=None)
+                    field_tol=1e-13, seed=0, lanczos_seed=1, bounds=None, kweights=None)
 
 
 def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons: float, kT: float,
             degree: int, coarse: Optional["Operator"] = None, max_hist: int = 1000, **kw):
     """The SCF loop of chfsi_scf_run.  rho, m (in: initial input densities; out: last
-    input), rho_out, m_out (out), X [2M][n_vec] (out: the Ritz block) are CUDA
-    tensors; bounds (optional) the filter's upper bound per iteration.  Returns
-    (history records as dicts, theta, occupations, converged)."""
+    input), rho_out, m_out (out) and X (out: the Ritz blocks; [2M][n_vec], or
+    [n_k][2M][n_vec] for an operator with n_k k-points) are CUDA tensors; bounds
+    (optional) the filter's upper bound per iteration and k-point (iteration-major),
+    kweights the k-point weights (default equal).  Returns (history records as dicts,
+    theta, occupations, converged); theta and the occupations are [n_k][n_vec] with
+    several k-points, [n_vec] with one."""
     o = dict(SCF_DEFAULTS)
     unknown = set(kw) - set(o)
     if unknown:
         raise TypeError(f"unknown SCF parameters {sorted(unknown)}")
     o.update(kw)
-    px, ldx, n = _block(X, "X")
+    nk = fine.n_k
+    torch = _torch()
+    if nk > 1:
+        if not isinstance(X, torch.Tensor) or X.dim() != 3 or X.shape[0] != nk or not X.is_contiguous():
+            raise ValueError("X must be a contiguous [n_k][2M][n_vec] tensor for several k-points")
+        px, ldx, n = _block(X[0], "X")
+    else:
+        px, ldx, n = _block(X, "X")
     prm = _lib.ScfParams()
     prm.n_vec, prm.degree = n, int(degree)
     for f in ("passes_first", "passes", "depth", "max_iter", "max_coarse", "lanczos_steps", "field_max_iter"):
@@ -382,13 +392,18 @@ def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons
     for f in ("alpha", "k0", "tol", "tol_coarse", "field_tol"):
         setattr(prm, f, float(o[f]))
     prm.seed, prm.lanczos_seed = int(o["seed"]), int(o["lanczos_seed"])
-    bnd = None
+    bnd = wk = None
     if o["bounds"] is not None:
         bnd = np.ascontiguousarray(np.asarray(o["bounds"], dtype=np.float64).reshape(-1))
         prm.bounds_h = bnd.ctypes.data_as(C.POINTER(C.c_double))
         prm.n_bounds = bnd.shape[0]
-    th = np.zeros(n)
-    occ = np.zeros(n)
+    if o["kweights"] is not None:
+        wk = np.ascontiguousarray(np.asarray(o["kweights"], dtype=np.float64).reshape(-1))
+        if wk.shape[0] != nk:
+            raise ValueError("kweights needs one weight per k-point")
+        prm.kweights_h = wk.ctypes.data_as(C.POINTER(C.c_double))
+    th = np.zeros(nk * n)
+    occ = np.zeros(nk * n)
     hist = (_lib.ScfRecord * max_hist)()
     nh, conv = C.c_int(), C.c_int()
     pd = C.POINTER(C.c_double)
@@ -400,6 +415,8 @@ def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons
                                 int(max_hist), C.byref(nh), C.byref(conv))
     _lib.check(rc, fine.ctx)
     recs = [{f: getattr(hist[i], f) for f, _ in _lib.ScfRecord._fields_} for i in range(min(nh.value, max_hist))]
+    if nk > 1:
+        th, occ = th.reshape(nk, n), occ.reshape(nk, n)
     return recs, th, occ, bool(conv.value)
 
 

@@ -184,15 +184,32 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
     CHFSI_CHECK(P.prec_mode == CHFSI_PREC_FP64 || P.prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL,
                 "scf_run: unknown precision");
     CHFSI_CHECK(((uintptr_t)X % 16) == 0, CHFSI_EINVAL, "scf_run: X_d must be 16-byte aligned");
+    const int nk = (int)fine->kp.size();
     std::vector<chfsi_ctx*> grids;
     if (coarse) {
       CHFSI_CHECK(fine->p == coarse->p + 1, CHFSI_EINVAL, "scf_run: the coarse degree must be the fine one - 1");
       CHFSI_CHECK(coarse->nq == fine->nq && coarse->quad == fine->quad && coarse->n_cells == fine->n_cells,
                   CHFSI_EINVAL, "scf_run: both grids need the same cells and quadrature points");
       CHFSI_CHECK(coarse->stream == fine->stream, CHFSI_EINVAL, "scf_run: the contexts must share a stream");
+      CHFSI_CHECK((int)coarse->kp.size() == nk, CHFSI_EINVAL, "scf_run: both grids need the same k-points");
+      for (int ik = 0; ik < nk; ++ik)
+        for (int d = 0; d < 3; ++d)
+          CHFSI_CHECK(coarse->kp[ik]->k[d] == fine->kp[ik]->k[d], CHFSI_EINVAL,
+                      "scf_run: both grids need the same k-points");
       grids.push_back(coarse);
     }
     grids.push_back(fine);
+    // zone-average weights of the k-points
+    std::vector<double> wk(nk, 1.0 / nk);
+    if (P.kweights_h) {
+      double ws = 0.0;
+      for (int ik = 0; ik < nk; ++ik) {
+        wk[ik] = P.kweights_h[ik];
+        CHFSI_CHECK(std::isfinite(wk[ik]) && wk[ik] >= 0.0, CHFSI_EINVAL, "scf_run: k-point weights must be >= 0");
+        ws += wk[ik];
+      }
+      CHFSI_CHECK(std::fabs(ws - 1.0) <= 1e-12, CHFSI_EINVAL, "scf_run: k-point weights must sum to 1");
+    }
     chfsi_ctx* c = fine;
     const int N = P.n_vec;
     const int64_t np = (int64_t)c->n_cells * c->nq3;
@@ -219,25 +236,37 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
     }
     DevBuf<double2> Xc, Wc, Wf, v0;
     if (coarse) {
-      Xc.alloc((size_t)2 * coarse->n_nodes * N);
+      Xc.alloc((size_t)nk * 2 * coarse->n_nodes * N);
       Wc.alloc((size_t)2 * coarse->n_nodes * N);
     }
     Wf.alloc((size_t)2 * fine->n_nodes * N);
     v0.alloc((size_t)2 * fine->n_nodes);
-    std::vector<double> theta(N), resid(N), occ(N);
+    // per k-point: Ritz values, residuals, occupations; occupations times weights
+    std::vector<double> theta((size_t)nk * N), resid(N), occ((size_t)nk * N), wts((size_t)nk * N), occw(N);
+    for (int ik = 0; ik < nk; ++ik)
+      for (int n = 0; n < N; ++n) wts[(size_t)ik * N + n] = wk[ik];
     int nh = 0, it = 0;
     bool conv = false;
     for (size_t gi = 0; gi < grids.size(); ++gi) {
       chfsi_ctx* g = grids[gi];
       c = g;                    // field solves in the FE space of the current grid
       const bool last = gi + 1 == grids.size();
-      void* Xg = last ? X : (void*)Xc.ptr;
       const int64_t ldg = last ? ldx : N;
+      // block of k-point ik on this grid
+      auto Xk = [&](int ik) -> void* {
+        return last ? (void*)((double2*)X + (size_t)ik * 2 * fine->n_nodes * ldx)
+                    : (void*)(Xc.ptr + (size_t)ik * 2 * coarse->n_nodes * N);
+      };
       void* Wg = last ? (void*)Wf.ptr : (void*)Wc.ptr;
-      if (gi == 0)
-        check_rc(chfsi_fill_random(g, Xg, 2 * g->n_nodes, N, ldg, P.seed, 0, 0, N), g, "scf_run: start block");
-      else
-        check_rc(chfsi_interpolate_block(grids[gi - 1], g, Xc.ptr, N, Xg, ldg, N), g, "scf_run: two-grid transfer");
+      for (int ik = 0; ik < nk; ++ik) {
+        if (gi == 0)
+          check_rc(chfsi_fill_random(g, Xk(ik), 2 * g->n_nodes, N, ldg, P.seed + 7919ull * (uint64_t)ik, 0, 0, N),
+                   g, "scf_run: start block");
+        else
+          check_rc(chfsi_interpolate_block(grids[gi - 1], g, Xc.ptr + (size_t)ik * 2 * coarse->n_nodes * N, N,
+                                           Xk(ik), ldg, N),
+                   g, "scf_run: two-grid transfer");
+      }
       int n_mix = 0;            // Anderson history is per grid
       int head = 0;             // ring slot of the next entry
       bool first = true;
@@ -250,35 +279,46 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
         field_axpby(c, np, 1.0, vext, 1.0, Vh.ptr, Vb.ptr);
         launch_exchange(c, np, rho, mag, Vb.ptr, bext, V.ptr, B.ptr);
         check_rc(chfsi_set_local(g, V.ptr, B.ptr), g, "scf_run: set_local");
-        double lo = 0.0, b = 0.0;
-        if (P.bounds_h && it - 1 < P.n_bounds) {
-          b = P.bounds_h[it - 1];
-          CHFSI_CHECK(std::isfinite(b), CHFSI_EINVAL, "scf_run: non-finite upper bound in bounds_h");
-        } else {
-          check_rc(chfsi_fill_random(g, v0.ptr, 2 * g->n_nodes, 1, 1, P.lanczos_seed, 0, 0, 1), g,
-                   "scf_run: Lanczos start");
-          check_rc(chfsi_lanczos_bounds(g, 0, P.lanczos_steps, v0.ptr, &lo, &b), g, "scf_run: Lanczos");
-        }
-        if (first) {
-          int bad = -1;
-          check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
-          check_rc(chfsi_rayleigh_ritz(g, 0, Xg, ldg, Wg, N, N, theta.data(), nullptr), g, "scf_run: RR");
-        }
         const int npass = (first && gi == 0) ? P.passes_first : P.passes;
-        for (int p = 0; p < npass; ++p) {
-          check_rc(chfsi_cheb_filter(g, 0, Xg, ldg, Wg, N, N, P.degree, theta[N - 1], b, theta[0], P.prec_mode), g,
-                   "scf_run: filter");
-          int bad = -1;
-          check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
-          check_rc(chfsi_rayleigh_ritz(g, 0, Xg, ldg, Wg, N, N, theta.data(), resid.data()), g, "scf_run: RR");
+        double b0 = 0.0;
+        for (int ik = 0; ik < nk; ++ik) {
+          double* th = theta.data() + (size_t)ik * N;
+          double lo = 0.0, b = 0.0;
+          const int64_t bi = (int64_t)(it - 1) * nk + ik;
+          if (P.bounds_h && bi < P.n_bounds) {
+            b = P.bounds_h[bi];
+            CHFSI_CHECK(std::isfinite(b), CHFSI_EINVAL, "scf_run: non-finite upper bound in bounds_h");
+          } else {
+            check_rc(chfsi_fill_random(g, v0.ptr, 2 * g->n_nodes, 1, 1, P.lanczos_seed, 0, 0, 1), g,
+                     "scf_run: Lanczos start");
+            check_rc(chfsi_lanczos_bounds(g, ik, P.lanczos_steps, v0.ptr, &lo, &b), g, "scf_run: Lanczos");
+          }
+          if (ik == 0) b0 = b;
+          void* Xg = Xk(ik);
+          if (first) {
+            int bad = -1;
+            check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
+            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, N, N, th, nullptr), g, "scf_run: RR");
+          }
+          for (int p = 0; p < npass; ++p) {
+            check_rc(chfsi_cheb_filter(g, ik, Xg, ldg, Wg, N, N, P.degree, th[N - 1], b, th[0], P.prec_mode), g,
+                     "scf_run: filter");
+            int bad = -1;
+            check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
+            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, N, N, th, resid.data()), g, "scf_run: RR");
+          }
         }
         first = false;
+        // one Fermi level for all (n, k); densities summed with the weights
         double mu = 0.0;
-        check_rc(chfsi_fermi_dirac(N, theta.data(), nullptr, P.n_electrons, P.kT, occ.data(), &mu, nullptr), nullptr,
-                 "scf_run: occupations");
+        check_rc(chfsi_fermi_dirac(nk * N, theta.data(), wts.data(), P.n_electrons, P.kT, occ.data(), &mu, nullptr),
+                 nullptr, "scf_run: occupations");
         field_fill(c, np, 0.0, ro.ptr);
         field_fill(c, 3 * np, 0.0, mo.ptr);
-        check_rc(chfsi_density(g, Xg, ldg, N, occ.data(), ro.ptr, mo.ptr), g, "scf_run: densities");
+        for (int ik = 0; ik < nk; ++ik) {
+          for (int n = 0; n < N; ++n) occw[n] = wk[ik] * occ[(size_t)ik * N + n];
+          check_rc(chfsi_density(g, Xk(ik), ldg, N, occw.data(), ro.ptr, mo.ptr), g, "scf_run: densities");
+        }
         // hold exactly N_e electrons under the cell quadrature
         const double q = P.n_electrons / field_integral(c, ro.ptr);
         CHFSI_CHECK(std::isfinite(q) && q > 0.0, CHFSI_ENONFINITE, "scf_run: output density has no positive charge");
@@ -288,10 +328,15 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
         field_axpby(c, 3 * np, 1.0, mo.ptr, -1.0, mag, fm.ptr);
         const double nres = std::sqrt(field_inner(c, fr.ptr, fm.ptr, fr.ptr, fm.ptr));
         CHFSI_CHECK(std::isfinite(nres), CHFSI_ENONFINITE, "scf_run: non-finite density residual");
-        double eband = 0.0;
-        for (int n = 0; n < N; ++n) eband += occ[n] * theta[n];
+        double eband = 0.0, th0 = theta[0];
+        for (int ik = 0; ik < nk; ++ik) {
+          double e = 0.0;
+          for (int n = 0; n < N; ++n) e += occ[(size_t)ik * N + n] * theta[(size_t)ik * N + n];
+          eband += wk[ik] * e;
+          th0 = std::min(th0, theta[(size_t)ik * N]);
+        }
         if (hist && nh < max_hist)
-          hist[nh] = chfsi_scf_record{g->p, nres, mu, eband, theta[0], cg_h, b};
+          hist[nh] = chfsi_scf_record{g->p, nres, mu, eband, th0, cg_h, b0};
         ++nh;
         conv = nres < (last ? P.tol : P.tol_coarse);
         if (last && (conv || it >= P.max_iter)) {

@@ -36,9 +36,9 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _op(nc, box, p, nq=None, atoms=(), form="cell"):
+def _op(nc, box, p, nq=None, atoms=(), form="cell", kpts=None):
     from paper_2410_02754_amd import Operator
-    op = Operator(nc, box, p, "gl", nq or p + 1, form=form)
+    op = Operator(nc, box, p, "gl", nq or p + 1, kpts, form=form)
     op.set_atoms(list(atoms))
     return op
 
@@ -122,7 +122,8 @@ def test_block_transfer_matches_oracle():
 def _compare_history(got, ref, rtol, atol, label):
     assert len(got) == len(ref), (len(got), len(ref))
     worst = 0.0
-    for g, (p, nres, mu, eb, th0, b) in zip(got, ref):
+    for g, r in zip(got, ref):
+        p, nres, mu, eb, th0 = r[:5]
         assert g["p"] == p
         d = abs(g["resid"] - nres)
         worst = max(worst, d / (atol + rtol * nres))
@@ -133,7 +134,8 @@ def _compare_history(got, ref, rtol, atol, label):
 
 
 def _bounds(ref):
-    return [h[5] for h in ref]
+    """The oracle's filter bounds, iteration-major over the k-points."""
+    return [b for h in ref for b in h[6]]
 
 
 def test_scf_uniform_gas_matches_oracle_and_closed_form():
@@ -226,5 +228,54 @@ def test_scf_two_grid_with_atoms_matches_oracle(form):
     d_th = np.abs(th2 - out["theta"])[occd].max()
     _say(f"[scf two-grid] own bounds: occupied Ritz values within {d_th:.1e} Ha")
     assert d_rho <= 1e-6 and d_th <= 1e-8
+    of.close()
+    oc.close()
+
+
+def test_scf_kpoint_sampling_two_grid_matches_oracle():
+    """Brillouin-zone sampling: two k-points of weights 0.3 and 0.7, each with its
+    own block, bound and passes, one Fermi level, densities summed with the
+    weights; two-grid start (every k-point's block moved to degree p).  Record by
+    record with the oracle's filter bounds, then the final densities, the
+    occupied Ritz values of both k-points and their occupations."""
+    from paper_2410_02754_amd import scf_run
+    kpts = [(0.0, 0.0, 0.7), (0.25, 0.0, -0.35)]
+    w = [0.3, 0.7]
+    kw_sys = dict(n_cells=(2, 2, 2), box=(4.5, 4.5, 4.5), n_atoms=2, lmax=1, rcut_sigmas=5.0, n_vec=8,
+                  degree=8, seed=5, kpts=kpts)
+    fine = synth.make_system("kscf", p=3, n_q=5, **kw_sys)
+    coarse = synth.make_system("kscf", p=2, n_q=5, **kw_sys)
+    mesh = ham.mesh_for(fine)
+    pts = mesh.all_quad_points().reshape(-1, 3)
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    vext = synth.veff(fine, pts).reshape(E, nq3)
+    bext = synth.bxc(fine, pts).reshape(E, nq3, 3)
+    # 3.4 electrons: the Fermi level sits in a partly filled level (with a whole number
+    # of filled levels it would lie anywhere in a gap, fixed only by rounding)
+    n_e, kT = 3.4, 2e-3
+    rho0 = np.full((E, nq3), n_e / 4.5 ** 3)
+    m0 = 0.05 * rho0[..., None] * np.array([0.6, 0.0, 0.8])
+    kw = dict(passes_first=5, passes=2, depth=4, alpha=0.5, k0=0.6, tol=1e-7, tol_coarse=1e-2, max_iter=60)
+    out = scf.scf(fine, vext, bext, rho0, m0, n_e, kT, coarse_system=coarse, kweights=w, **kw)
+    of = _op(fine.n_cells, fine.box, 3, 5, fine.atoms, kpts=kpts)
+    oc = _op(coarse.n_cells, coarse.box, 2, 5, coarse.atoms, kpts=kpts)
+    rho, m = _dev(rho0), _dev(m0)
+    ro, mo = torch.empty_like(rho), torch.empty_like(m)
+    X = torch.empty((2, of.n_dof, 8), dtype=torch.complex128, device="cuda")
+    hist, th, occ, conv = scf_run(of, _dev(vext), _dev(bext), rho, m, ro, mo, X, n_e, kT, 8, coarse=oc, seed=0,
+                                  lanczos_seed=fine.seed + 1, bounds=_bounds(out["history"]), kweights=w, **kw)
+    _say(f"[scf k-points] gpu {len(hist)} iterations; oracle {len(out['history'])}")
+    for g, r in zip(hist, out["history"]):
+        _say(f"   p{g['p']} gpu {g['resid']:.6e} oracle {r[1]:.6e} d={abs(g['resid'] - r[1]):.1e} "
+             f"mu d={abs(g['mu'] - r[2]):.1e}")
+    assert conv and out["converged"]
+    _compare_history(hist, out["history"], 1e-6, 1e-11, "scf k-points")
+    for got, ref in ((ro, out["rho_out"]), (mo, out["m_out"]), (rho, out["rho_in"]), (m, out["m_in"])):
+        assert np.abs(got.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
+    occd = out["occ_k"] > 1e-12
+    assert th.shape == (2, 8) and np.abs(th - out["theta_k"])[occd].max() <= 1e-9
+    assert np.abs(occ - out["occ_k"]).max() <= 1e-8
+    # the weights enter: both k-points hold electrons, in the ratio of the zone average
+    assert abs(float(np.dot(w, occ.sum(axis=1))) - n_e) < 1e-10
     of.close()
     oc.close()
