@@ -241,8 +241,8 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
     }
     Wf.alloc((size_t)2 * fine->n_nodes * N);
     v0.alloc((size_t)2 * fine->n_nodes);
-    // per k-point: Ritz values, residuals, occupations; occupations times weights
-    std::vector<double> theta((size_t)nk * N), resid(N), occ((size_t)nk * N), wts((size_t)nk * N), occw(N);
+    // per k-point: Ritz values and occupations; occupations times weights
+    std::vector<double> theta((size_t)nk * N), occ((size_t)nk * N), wts((size_t)nk * N), occw(N);
     for (int ik = 0; ik < nk; ++ik)
       for (int n = 0; n < N; ++n) wts[(size_t)ik * N + n] = wk[ik];
     int nh = 0, it = 0;
@@ -305,7 +305,8 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
                      "scf_run: filter");
             int bad = -1;
             check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
-            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, N, N, th, resid.data()), g, "scf_run: RR");
+            // residual norms are not needed here: no rotation of H X
+            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, N, N, th, nullptr), g, "scf_run: RR");
           }
         }
         first = false;
