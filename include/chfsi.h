@@ -361,7 +361,11 @@ typedef struct {
   int max_coarse;       /* iterations on the coarse grid at most                     */
   int lanczos_steps;    /* Lanczos steps for the upper bound, every iteration        */
   int field_max_iter;   /* conjugate-gradient steps per field solve at most          */
-  int prec_mode;        /* filter precision, CHFSI_PREC_FP64 or CHFSI_PREC_MIXED     */
+  int prec_mode;        /* CHFSI_PREC_FP64, or CHFSI_PREC_MIXED: the residual form of
+                           the filter (chfsi_cheb_filter_resid, FP32 products on the
+                           residuals; R formed in FP64 at the start of every iteration
+                           and after every Rayleigh-Ritz), which converges as far as
+                           FP64 where FP32 products on the whole block stall        */
   double n_electrons;   /* 0 < N_e < n_vec                                           */
   double kT;            /* Fermi-Dirac smearing, Ha                                  */
   double alpha;         /* mixing parameter                                          */

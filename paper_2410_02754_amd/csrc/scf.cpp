@@ -234,15 +234,21 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
       hf[j].alloc(np);
       hfm[j].alloc(3 * np);
     }
-    DevBuf<double2> Xc, Wc, Wf, v0;
+    // mixed precision runs the residual form of the filter: its work blocks are two
+    // columns wide per state, and the residual block R = H X - X diag(theta) is kept
+    const bool resid_form = P.prec_mode == CHFSI_PREC_MIXED;
+    const int wcols = resid_form ? 2 * N : N;
+    DevBuf<double2> Xc, Wc, Wf, Rc, Rf, v0;
     if (coarse) {
       Xc.alloc((size_t)nk * 2 * coarse->n_nodes * N);
-      Wc.alloc((size_t)2 * coarse->n_nodes * N);
+      Wc.alloc((size_t)2 * coarse->n_nodes * wcols);
+      if (resid_form) Rc.alloc((size_t)2 * coarse->n_nodes * N);
     }
-    Wf.alloc((size_t)2 * fine->n_nodes * N);
+    Wf.alloc((size_t)2 * fine->n_nodes * wcols);
+    if (resid_form) Rf.alloc((size_t)2 * fine->n_nodes * N);
     v0.alloc((size_t)2 * fine->n_nodes);
     // per k-point: Ritz values and occupations; occupations times weights
-    std::vector<double> theta((size_t)nk * N), occ((size_t)nk * N), wts((size_t)nk * N), occw(N);
+    std::vector<double> theta((size_t)nk * N), occ((size_t)nk * N), wts((size_t)nk * N), occw(N), rnorm(N);
     for (int ik = 0; ik < nk; ++ik)
       for (int n = 0; n < N; ++n) wts[(size_t)ik * N + n] = wk[ik];
     int nh = 0, it = 0;
@@ -258,6 +264,7 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
                     : (void*)(Xc.ptr + (size_t)ik * 2 * coarse->n_nodes * N);
       };
       void* Wg = last ? (void*)Wf.ptr : (void*)Wc.ptr;
+      void* Rg = last ? (void*)Rf.ptr : (void*)Rc.ptr;
       for (int ik = 0; ik < nk; ++ik) {
         if (gi == 0)
           check_rc(chfsi_fill_random(g, Xk(ik), 2 * g->n_nodes, N, ldg, P.seed + 7919ull * (uint64_t)ik, 0, 0, N),
@@ -298,15 +305,31 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
           if (first) {
             int bad = -1;
             check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
-            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, N, N, th, nullptr), g, "scf_run: RR");
+            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, wcols, N, th, nullptr), g, "scf_run: RR");
+          }
+          if (resid_form) {
+            // R = H X - X diag(theta) for this iteration's operator (FP64)
+            check_rc(chfsi_apply_H(g, ik, Xg, ldg, Rg, N, N, CHFSI_PREC_FP64), g, "scf_run: residual apply");
+            check_rc(chfsi_ritz_residual(g, Xg, ldg, Rg, N, N, th), g, "scf_run: residuals");
           }
           for (int p = 0; p < npass; ++p) {
-            check_rc(chfsi_cheb_filter(g, ik, Xg, ldg, Wg, N, N, P.degree, th[N - 1], b, th[0], P.prec_mode), g,
-                     "scf_run: filter");
+            if (resid_form)
+              check_rc(chfsi_cheb_filter_resid(g, ik, Xg, ldg, Rg, N, th, Wg, wcols, N, P.degree, th[N - 1], b, th[0],
+                                               CHFSI_PREC_MIXED),
+                       g, "scf_run: filter");
+            else
+              check_rc(chfsi_cheb_filter(g, ik, Xg, ldg, Wg, wcols, N, P.degree, th[N - 1], b, th[0], P.prec_mode), g,
+                       "scf_run: filter");
             int bad = -1;
             check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
-            // residual norms are not needed here: no rotation of H X
-            check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, N, N, th, nullptr), g, "scf_run: RR");
+            if (resid_form) {
+              // H X of the rotated block into R, then R = H X - X diag(theta)
+              check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Rg, N, N, th, rnorm.data()), g, "scf_run: RR");
+              check_rc(chfsi_ritz_residual(g, Xg, ldg, Rg, N, N, th), g, "scf_run: residuals");
+            } else {
+              // residual norms are not needed here: no rotation of H X
+              check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, wcols, N, th, nullptr), g, "scf_run: RR");
+            }
           }
         }
         first = false;

@@ -279,3 +279,49 @@ def test_scf_kpoint_sampling_two_grid_matches_oracle():
     assert abs(float(np.dot(w, occ.sum(axis=1))) - n_e) < 1e-10
     of.close()
     oc.close()
+
+
+def test_scf_mixed_precision_reaches_the_fp64_fixed_point():
+    """Mixed precision in the SCF loop runs the residual form of the filter (FP32
+    products on H x residual only, Sec. III.B.2): the loop converges as far as the
+    FP64 one (to 1e-9 here, where FP32 products on the whole block stall near
+    3e-8) and lands on the oracle's fixed point."""
+    from paper_2410_02754_amd import scf_run
+    kw_sys = dict(n_cells=(2, 2, 2), box=(5.0, 5.0, 5.0), n_atoms=2, lmax=1, rcut_sigmas=5.0, n_vec=10,
+                  degree=8, seed=6)
+    fine = synth.make_system("scf", p=3, n_q=5, **kw_sys)
+    coarse = synth.make_system("scf", p=2, n_q=5, **kw_sys)
+    mesh = ham.mesh_for(fine)
+    pts = mesh.all_quad_points().reshape(-1, 3)
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    vext = synth.veff(fine, pts).reshape(E, nq3)
+    bext = synth.bxc(fine, pts).reshape(E, nq3, 3)
+    n_e, kT = 5.0, 500 * 3.166811563e-6
+    rho0 = np.full((E, nq3), n_e / 125.0)
+    m0 = 0.2 * bext / 0.1 * rho0[..., None]
+    kw = dict(passes_first=5, passes=2, depth=5, alpha=0.5, k0=0.8, tol=1e-9, tol_coarse=1e-2, max_iter=50)
+    out = scf.scf(fine, vext, bext, rho0, m0, n_e, kT, coarse_system=coarse, **kw)
+    of = _op(fine.n_cells, fine.box, 3, 5, fine.atoms)
+    oc = _op(coarse.n_cells, coarse.box, 2, 5, coarse.atoms)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        rho, m = _dev(rho0), _dev(m0)
+        ro, mo = torch.empty_like(rho), torch.empty_like(m)
+        X = torch.empty((of.n_dof, 10), dtype=torch.complex128, device="cuda")
+        hist, th, occ, conv = scf_run(of, _dev(vext), _dev(bext), rho, m, ro, mo, X, n_e, kT, 8, coarse=oc, seed=0,
+                                      lanczos_seed=fine.seed + 1, prec=prec, **kw)
+        _say(f"[scf {prec}] {len(hist)} iterations, residual {hist[-1]['resid']:.2e}, converged {conv}")
+        assert conv
+        res[prec] = (len(hist), ro.cpu().numpy(), mo.cpu().numpy(), th, occ)
+    n64, r64, m64, t64, o64 = res["fp64"]
+    nmx, rmx, mmx, tmx, omx = res["mixed"]
+    d_rho = np.abs(rmx - r64).max() / np.abs(r64).max()
+    d_ref = np.abs(rmx - out["rho_out"]).max() / np.abs(out["rho_out"]).max()
+    occd = o64 > 0.5
+    d_th = np.abs(tmx - t64)[occd].max()
+    _say(f"[scf mixed] rho vs FP64 {d_rho:.1e}, vs oracle {d_ref:.1e}; occupied theta {d_th:.1e} Ha")
+    assert abs(nmx - n64) <= 2
+    assert d_rho <= 1e-9 and d_ref <= 1e-8 and d_th <= 1e-9
+    assert np.abs(mmx - m64).max() <= 1e-9 * np.abs(r64).max()
+    of.close()
+    oc.close()
