@@ -28,6 +28,12 @@ Printed JSON (one line, rank 0):
                1e-7 Ha bar of the FP32 forms); fastest_pass_within_1e-7_Ha uses it
   density      rho and m of the Ritz block with 500 K occupations
   cpu_baseline the FP64 oracle timed on the host (see cpu_baseline())
+  paper_context the paper's own figures (whole SCF iterations), context only
+
+Other workloads (--workload): batch (k-grid + uneven systems in one captured launch),
+small systems inside it, adjoint (filter and its adjoint), scf (seconds per SCF
+iteration on the k-grid system, FP64 and mixed), kernels (every hot kernel once, for
+profilers).
 """
 from __future__ import annotations
 
@@ -325,8 +331,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=os.environ.get("CHFSI_BENCH_WORKLOAD", "scale"),
-                    help="scale (default), batch (k-grid + uneven systems), adjoint, or kernels "
-                         "(a short run of every hot kernel on the large mesh, for profilers)")
+                    help="scale (default), batch (k-grid + uneven systems), adjoint, scf (the SCF loop "
+                         "on the k-grid system), or kernels (a short run of every hot kernel on the "
+                         "large mesh, for profilers)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-matfree", action="store_true")
@@ -346,10 +353,124 @@ def main():
         out = bench_kernels(args, torch)
     elif args.workload == "adjoint":
         out = bench_adjoint(args, torch)
+    elif args.workload == "scf":
+        out = bench_scf(args, torch)
     else:
         out = bench_scale(args, torch)
         out["paper_context"] = PAPER_CONTEXT
     print(json.dumps(out), flush=True)
+
+
+def bench_scf(args, torch, n_iter=3):
+    """The SCF loop (Sec. III.B, with the zone average of Sec. II.C) on the k-sampled
+    system of the batched workload: 12^3 cells, p = 5, the 8 k-points of a 2x2x2
+    Monkhorst-Pack grid (equal weights), 27 spin-orbit pseudo-atoms (l <= 1), N = 384,
+    degree 16, N_e = 0.85 N electrons at 500 K, the stand-in map (Hartree with a
+    uniform background + LSDA exchange), Anderson depth 4 with Kerker.  One SCF
+    iteration = per k-point a Lanczos bound (40 steps) and one ChFSI pass (filter,
+    CholGS, Rayleigh-Ritz), then one Fermi level, the densities of all k-points, the
+    field solves and the mixing.  Timed: n_iter iterations restarted from the state of
+    a two-iteration warm-up (the first timed iteration also orthonormalises the given
+    blocks), FP64 and mixed precision (the loop's residual form of the filter); the
+    oracle's SCF iteration on a small k-sampled system is timed on the host."""
+    import synth
+    from paper_2410_02754_amd import scf_run
+    kg = synth.config("kgrid")
+    nk, N = len(kg.kpts), kg.n_vec
+    n_e, kT = 0.85 * N, 500 * K_B_HA
+    t = time.perf_counter()
+    op = build_operator(kg, torch)
+    t_setup = time.perf_counter() - t
+    pts = op.quad_points().reshape(-1, 3)
+    vext = torch.tensor(synth.veff(kg, pts).reshape(op.n_cells, op.nq3), device="cuda")
+    bext = torch.tensor(synth.bxc(kg, pts).reshape(op.n_cells, op.nq3, 3), device="cuda")
+    vol = float(np.prod(kg.box))
+    X = torch.empty((nk, op.n_dof, N), dtype=torch.complex128, device="cuda")
+    kw = dict(passes_first=1, passes=1, depth=4, alpha=0.5, k0=0.6, tol=1e-30, tol_coarse=1e-30,
+              field_tol=1e-12, seed=kg.seed, lanczos_seed=kg.seed + 1)
+    out = {"metric": "s per SCF iteration (k-sampled: ChFSI per k-point, one Fermi level, densities, "
+                     "stand-in map, Anderson + Kerker)",
+           "unit": "s", "higher_is_better": False, "n_gpus": 1, "steps": n_iter, "warmup": 2,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"scf: 12^3 cells p=5 (h=1.2 bohr), 2x2x2 Monkhorst-Pack ({nk} k-points), "
+                                  f"{len(kg.atoms)} SOC atoms l<=1, N={N}, N_e={n_e:.1f}, degree {kg.degree}, "
+                                  "one ChFSI pass per k-point and iteration",
+                      "parallelism": "single GPU"},
+           "setup_s": round(t_setup, 2)}
+    # warm-up: two iterations from the seeded blocks (three passes in the first); the
+    # timed runs restart from that state (blocks and densities restored for each form)
+    rho = torch.full((op.n_cells, op.nq3), n_e / vol, dtype=torch.float64, device="cuda")
+    m = torch.zeros((op.n_cells, op.nq3, 3), dtype=torch.float64, device="cuda")
+    m[..., 2] = 0.1 * rho
+    ro, mo = torch.empty_like(rho), torch.empty_like(m)
+    t0 = time.perf_counter()
+    scf_run(op, vext, bext, rho, m, ro, mo, X, n_e, kT, kg.degree, max_iter=2, prec="fp64",
+            **dict(kw, passes_first=3))
+    torch.cuda.synchronize()
+    log(f"[bench] scf warm-up (2 iterations): {time.perf_counter() - t0:.1f} s")
+    X_w, rho_w, m_w = X.clone(), rho.clone(), m.clone()
+    for prec in (("fp64",) if args.no_mixed else ("fp64", "mixed")):
+        res = {}
+        for label, iters in (("timed", n_iter),):
+            X.copy_(X_w)
+            rho.copy_(rho_w)
+            m.copy_(m_w)
+            op.stats_enable(True)
+            op.stats_reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hist, th, occ, conv = scf_run(op, vext, bext, rho, m, ro, mo, X, n_e, kT, kg.degree,
+                                          max_iter=iters, prec=prec, start_given=True, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if label == "timed":
+                st = op.stats()
+                op.stats_enable(False)
+                stage = {k: round(v["ms"] / iters, 1) for k, v in st.items() if v["launches"] or v["ms"]}
+                res = {"s_per_iteration": round(dt / iters, 3),
+                       "stage_ms_per_iteration": stage,
+                       "other_ms_per_iteration": round(1e3 * dt / iters - sum(stage.values()), 1),
+                       "residual_norms": [float(f"{h['resid']:.3e}") for h in hist],
+                       "mu_Ha": hist[-1]["mu"], "theta0_Ha": hist[-1]["theta0"],
+                       "hartree_cg_steps": [h["hartree_iters"] for h in hist]}
+                log(f"[bench] scf {prec}: {dt / iters:.3f} s per iteration, residuals "
+                    + " ".join(f"{h['resid']:.2e}" for h in hist))
+        out[prec if prec == "fp64" else "mixed_resid"] = res
+    out["value"] = out["fp64"]["s_per_iteration"]
+    out["ms_per_step"] = round(1e3 * out["value"], 1)
+    if "mixed_resid" in out:
+        out["speedup_mixed_resid"] = round(out["fp64"]["s_per_iteration"] / out["mixed_resid"]["s_per_iteration"], 3)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_scf()
+    return out
+
+
+def cpu_baseline_scf(n_iter=3):
+    """The oracle's SCF loop as it stands, timed on the host: the mesh of the tiny
+    workload (3^3 cells, p = 4, L = 8 bohr) with two k-points, two SOC atoms (l <= 1),
+    N = 32, degree 10, n_iter iterations of one ChFSI pass per k-point (scipy CSR
+    products on one core, dense steps through numpy's BLAS)."""
+    import synth
+    from oracle import hamiltonian as ham, scf as oscf
+    s = synth.make_system("kscf", n_cells=(3, 3, 3), box=(8.0, 8.0, 8.0), p=4, n_atoms=2, lmax=1,
+                          n_vec=32, degree=10, seed=5, kpts=[(0.0, 0.0, 0.39), (0.2, 0.0, -0.2)])
+    mesh = ham.mesh_for(s)
+    pts = mesh.all_quad_points().reshape(-1, 3)
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    vext = synth.veff(s, pts).reshape(E, nq3)
+    bext = synth.bxc(s, pts).reshape(E, nq3, 3)
+    n_e = 0.85 * s.n_vec
+    rho0 = np.full((E, nq3), n_e / 512.0)
+    m0 = np.zeros((E, nq3, 3))
+    m0[..., 2] = 0.1 * rho0
+    t = time.perf_counter()
+    oscf.scf(s, vext, bext, rho0, m0, n_e, 500 * K_B_HA, passes_first=1, passes=1, max_iter=n_iter, tol=1e-30)
+    dt = time.perf_counter() - t
+    return {"value": round(dt / n_iter, 3), "unit": "s per SCF iteration", "kind": "oracle",
+            "cores": _host_threads(),
+            "sample": f"{n_iter} oracle SCF iterations on 3^3 cells p=4 ({s.n_dof} dofs), 2 k-points, "
+                      f"2 SOC atoms, N={s.n_vec}, degree {s.degree} (CSR products on one core, dense steps up "
+                      f"to {_host_threads()} threads)"}
 
 
 def bench_kernels(args, torch):

@@ -382,6 +382,8 @@ typedef struct {
   int n_bounds;         /* entries of bounds_h (iterations past them use Lanczos)    */
   const double* kweights_h;/* host [n_k]: zone-average weights of the context's k-points
                           (>= 0, summing to 1), or NULL: equal weights           */
+  int start_given;      /* 1: X_d holds the start blocks (a restart; no coarse grid),
+                          0: the seeded start blocks                             */
 } chfsi_scf_params;
 
 typedef struct {
@@ -409,7 +411,9 @@ typedef struct {
  * their atoms set.
  * Brillouin-zone sampling (Sec. II.C): every k-point of the fine context (the
  * coarse one must have the same k-points) carries its own block, Lanczos bound
- * and ChFSI passes; the occupations f_nk have one Fermi level for all (n, k)
+ * and ChFSI passes (start: the seeded block, or the caller's block in X_d with
+ * start_given, which the first iteration orthonormalises before its
+ * Rayleigh-Ritz); the occupations f_nk have one Fermi level for all (n, k)
  * with sum_k w_k sum_n f_nk = N_e (chfsi_fermi_dirac with weights w_k), and the
  * output densities are sum_k w_k sum_n f_nk |u_nk|^2 (likewise m).  The start
  * block of k-point ik is the chfsi_fill_random stream of seed + 7919 ik.

@@ -48,7 +48,7 @@ class ScfParams(C.Structure):
                 ("kT", C.c_double), ("alpha", C.c_double), ("k0", C.c_double), ("tol", C.c_double),
                 ("tol_coarse", C.c_double), ("field_tol", C.c_double), ("seed", C.c_uint64),
                 ("lanczos_seed", C.c_uint64), ("bounds_h", C.POINTER(C.c_double)), ("n_bounds", C.c_int),
-                ("kweights_h", C.POINTER(C.c_double))]
+                ("kweights_h", C.POINTER(C.c_double)), ("start_given", C.c_int)]
 
 
 class ScfRecord(C.Structure):

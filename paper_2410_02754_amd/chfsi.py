@@ -358,7 +358,7 @@ def interpolate_block(coarse: "Operator", fine: "Operator", Yc, Yf):
 
 SCF_DEFAULTS = dict(passes_first=4, passes=1, depth=4, max_iter=40, max_coarse=20, lanczos_steps=40,
                     field_max_iter=20000, prec="fp64", alpha=0.5, k0=0.0, tol=1e-8, tol_coarse=1e-3,
-                    field_tol=1e-13, seed=0, lanczos_seed=1, bounds=None, kweights=None)
+                    field_tol=1e-13, seed=0, lanczos_seed=1, bounds=None, kweights=None, start_given=False)
 
 
 def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons: float, kT: float,
@@ -367,7 +367,8 @@ def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons
     input), rho_out, m_out (out) and X (out: the Ritz blocks; [2M][n_vec], or
     [n_k][2M][n_vec] for an operator with n_k k-points) are CUDA tensors; bounds
     (optional) the filter's upper bound per iteration and k-point (iteration-major),
-    kweights the k-point weights (default equal).  Returns (history records as dicts,
+    kweights the k-point weights (default equal); start_given: X holds the start
+    blocks (a restart) instead of the seeded ones.  Returns (history records as dicts,
     theta, occupations, converged); theta and the occupations are [n_k][n_vec] with
     several k-points, [n_vec] with one."""
     o = dict(SCF_DEFAULTS)
@@ -392,6 +393,7 @@ def scf_run(fine: "Operator", vext, bext, rho, m, rho_out, m_out, X, n_electrons
     for f in ("alpha", "k0", "tol", "tol_coarse", "field_tol"):
         setattr(prm, f, float(o[f]))
     prm.seed, prm.lanczos_seed = int(o["seed"]), int(o["lanczos_seed"])
+    prm.start_given = 1 if o["start_given"] else 0
     bnd = wk = None
     if o["bounds"] is not None:
         bnd = np.ascontiguousarray(np.asarray(o["bounds"], dtype=np.float64).reshape(-1))

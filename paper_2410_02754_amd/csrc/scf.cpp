@@ -184,6 +184,8 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
     CHFSI_CHECK(P.prec_mode == CHFSI_PREC_FP64 || P.prec_mode == CHFSI_PREC_MIXED, CHFSI_EINVAL,
                 "scf_run: unknown precision");
     CHFSI_CHECK(((uintptr_t)X % 16) == 0, CHFSI_EINVAL, "scf_run: X_d must be 16-byte aligned");
+    CHFSI_CHECK(P.start_given == 0 || (P.start_given == 1 && coarse == nullptr), CHFSI_EINVAL,
+                "scf_run: start_given is 0 or 1, and a given start block needs no coarse grid");
     const int nk = (int)fine->kp.size();
     std::vector<chfsi_ctx*> grids;
     if (coarse) {
@@ -266,6 +268,7 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
       void* Wg = last ? (void*)Wf.ptr : (void*)Wc.ptr;
       void* Rg = last ? (void*)Rf.ptr : (void*)Rc.ptr;
       for (int ik = 0; ik < nk; ++ik) {
+        if (gi == 0 && P.start_given) continue;   // the caller's blocks
         if (gi == 0)
           check_rc(chfsi_fill_random(g, Xk(ik), 2 * g->n_nodes, N, ldg, P.seed + 7919ull * (uint64_t)ik, 0, 0, N),
                    g, "scf_run: start block");

@@ -325,3 +325,36 @@ def test_scf_mixed_precision_reaches_the_fp64_fixed_point():
     assert np.abs(mmx - m64).max() <= 1e-9 * np.abs(r64).max()
     of.close()
     oc.close()
+
+
+def test_scf_restart_from_given_blocks_matches_oracle():
+    """start_given: the loop continues from the caller's block and densities (here the
+    state left by four iterations), as the oracle does from the same X0, rho0, m0."""
+    from paper_2410_02754_amd import scf_run
+    fine = synth.make_system("scf", p=3, n_q=5, n_cells=(2, 2, 2), box=(5.0, 5.0, 5.0), n_atoms=2, lmax=1,
+                             rcut_sigmas=5.0, n_vec=10, degree=8, seed=6)
+    mesh = ham.mesh_for(fine)
+    pts = mesh.all_quad_points().reshape(-1, 3)
+    E, nq3 = mesh.n_cell_total, mesh.nq ** 3
+    vext = synth.veff(fine, pts).reshape(E, nq3)
+    bext = synth.bxc(fine, pts).reshape(E, nq3, 3)
+    n_e, kT = 5.0, 500 * 3.166811563e-6
+    rho0 = np.full((E, nq3), n_e / 125.0)
+    m0 = 0.2 * bext / 0.1 * rho0[..., None]
+    of = _op(fine.n_cells, fine.box, 3, 5, fine.atoms)
+    rho, m = _dev(rho0), _dev(m0)
+    ro, mo = torch.empty_like(rho), torch.empty_like(m)
+    X = torch.empty((of.n_dof, 10), dtype=torch.complex128, device="cuda")
+    kw = dict(passes_first=3, passes=2, depth=4, alpha=0.5, k0=0.8, tol=1e-30)
+    scf_run(of, _dev(vext), _dev(bext), rho, m, ro, mo, X, n_e, kT, 8, seed=0, lanczos_seed=fine.seed + 1,
+            max_iter=4, **kw)
+    X0, r0, mm0 = X.cpu().numpy(), rho.cpu().numpy(), m.cpu().numpy()
+    out = scf.scf(fine, vext, bext, r0, mm0, n_e, kT, X0=X0, max_iter=5, **kw)
+    hist, th, occ, conv = scf_run(of, _dev(vext), _dev(bext), rho, m, ro, mo, X, n_e, kT, 8,
+                                  lanczos_seed=fine.seed + 1, max_iter=5, start_given=True,
+                                  bounds=_bounds(out["history"]), **kw)
+    for g, r in zip(hist, out["history"]):
+        _say(f"   restart gpu {g['resid']:.6e} oracle {r[1]:.6e} d={abs(g['resid'] - r[1]):.1e}")
+    _compare_history(hist, out["history"], 1e-6, 1e-11, "scf restart")
+    assert np.abs(ro.cpu().numpy() - out["rho_out"]).max() <= 1e-9 * np.abs(out["rho_out"]).max()
+    of.close()
