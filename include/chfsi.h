@@ -246,7 +246,9 @@ size_t chfsi_workspace_bytes(const chfsi_ctx* ctx, int ik, int n_vec, int op);
 /* Spectral bounds by `steps` Lanczos steps on H_hat^k from v0_d [2M]
  * (complex128, device, not modified): *lo = smallest Ritz value of the
  * tridiagonal, *hi = largest Ritz value + ||f_steps|| (an upper bound of the
- * spectrum, Sec. III.B.2). */
+ * spectrum, Sec. III.B.2).  In the cell-matrix form (when n_q = p + 1) the
+ * single-column applies run the matrix-free product of the same operator, which
+ * does not stream the cell matrices for one column. */
 int chfsi_lanczos_bounds(chfsi_ctx* ctx, int ik, int steps, const void* v0_d, double* lo,
                          double* hi);
 

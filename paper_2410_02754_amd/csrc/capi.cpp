@@ -204,6 +204,10 @@ int chfsi_set_local(chfsi_ctx* c, const double* V, const double* B) {
     launch_cell_to_f32(c, *kp);
     CHFSI_HIP(hipStreamSynchronize(c->stream));
   }
+  // the matrix-free quadrature data as well (w_q J (V, B) per point, 32 B): the
+  // single-column applies of the Lanczos bounds use it instead of streaming the
+  // cell operators for one column
+  if (mf_supported(c)) mf_set_local(c, V, B);
   c->have_local = true;
   API_END(c)
 }
@@ -526,6 +530,15 @@ int chfsi_lanczos_bounds(chfsi_ctx* c, int ik, int steps, const void* v0, double
   launch_axpby_rows(c, vp, 1, v, 1, rows, 1, 0.0, 0.0);
   double beta = 0.0;
   std::vector<double> al, be;
+  // one column per apply: with the matrix-free data of the current fields at
+  // hand the local part takes the matrix-free product (the same operator up to
+  // rounding), which reads no cell matrices
+  struct FormGuard {
+    chfsi_ctx* c;
+    int form;
+    ~FormGuard() { c->form = form; }
+  } fg{c, c->form};
+  if (c->form == CHFSI_FORM_CELL_MATRIX && c->mf_gen == c->gen) c->form = CHFSI_FORM_MATRIX_FREE;
   for (int j = 0; j < steps; ++j) {
     apply_H(c, kp, v, 1, w, 1, 1, CHFSI_PREC_FP64, 1.0, 0.0, 0.0);
     const double alpha = dot_re(c, v, w, rows);

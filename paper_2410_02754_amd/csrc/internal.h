@@ -196,6 +196,7 @@ struct chfsi_ctx {
   // bumped by every call that rebuilds device operator data (set_local, set_atoms,
   // set_apply_form): objects holding its device pointers check it before use
   uint64_t gen = 0;
+  uint64_t mf_gen = 0;                        // gen of the last matrix-free quadrature data (0: none)
   // internal scratch
   chfsi::DevBuf<double> scratch;              // reductions, small matrices
   // when set, the nonlocal coefficients of every apply use this fixed buffer

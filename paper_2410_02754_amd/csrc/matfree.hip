@@ -454,6 +454,7 @@ void mf_set_local(chfsi_ctx* c, const double* V, const double* B) {
                      reinterpret_cast<float4*>(c->mf_qd32.ptr));
   LAUNCH_CHECK();
   CHFSI_HIP(hipStreamSynchronize(c->stream));
+  c->mf_gen = c->gen;
 }
 
 void launch_mf_products(chfsi_ctx* c, const KPoint& kp, int prec, const double2* X, int64_t ldx, double2* W,
