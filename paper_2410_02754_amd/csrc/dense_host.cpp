@@ -7,7 +7,9 @@
 //    tridiagonal matrix (Golub and Van Loan, Sec. 8.3), a diagonal phase
 //    change that makes it real, then the implicit QL iteration with shifts on
 //    the real tridiagonal (Bowdler, Martin, Reinsch and Wilkinson, 1968),
-//    accumulating the rotations, and back-transformation.
+//    accumulating the rotations, and back-transformation by blocks of
+//    reflectors in the compact WY form I - Y T Y^H (Schreiber and Van Loan,
+//    1989).
 // All matrices are row-major std::vector<cplx> of size n*n.
 #include <algorithm>
 #include <atomic>
@@ -337,33 +339,99 @@ void hermitian_eig(const std::vector<cplx>& Ain, int n, std::vector<double>& w, 
     const double* z = &Zt[(size_t)order[j] * n];
     for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = phi[i] * z[i];
   }
-  // Q = H_0 H_1 ... H_{n-3}; apply in reverse to the rows k+1.. of V, each
-  // worker on its own range of columns (the columns are independent)
+  // Q = H_0 H_1 ... H_{n-3} applied to V, H_k = I - 2 v_k v_k^H (v_k unit, nonzero
+  // from row k+1).  The reflectors go in blocks of kWY consecutive ones, each block
+  // H_k1 ... H_k2 = I - Y T Y^H (compact WY form: Y = [v_k1 .. v_k2], T upper
+  // triangular, T_ii = 2, T[0:i, i] = -2 T[0:i, 0:i] (Y[:, 0:i]^H v_i)), applied as
+  // V_sub -= Y (T (Y^H V_sub)), last block first; each worker takes its own range of
+  // columns (the columns are independent).
+  constexpr int kWY = 32;
+  const int nref = std::max(0, n - 2);
+  struct Blk {
+    int k1, k2;                 // reflectors k1..k2
+    std::vector<cplx> Y;        // [m1][nb], rows k1+1 .. n-1 (zero above each v's start)
+    std::vector<cplx> T;        // [nb][nb] upper
+  };
+  std::vector<Blk> blks;
+  for (int k1 = 0; k1 < nref; k1 += kWY) {
+    Blk B;
+    B.k1 = k1;
+    B.k2 = std::min(nref, k1 + kWY) - 1;
+    const int nb = B.k2 - B.k1 + 1, m1 = n - k1 - 1;
+    B.Y.assign((size_t)m1 * nb, 0.0);
+    for (int j = 0; j < nb; ++j) {
+      const auto& v = vs[k1 + j];
+      if (v.empty()) continue;
+      for (size_t i = 0; i < v.size(); ++i) B.Y[(size_t)(j + i) * nb + j] = v[i];   // v_k starts at row k+1
+    }
+    B.T.assign((size_t)nb * nb, 0.0);
+    std::vector<cplx> g(nb);
+    for (int i = 0; i < nb; ++i) {
+      if (vs[k1 + i].empty()) continue;      // H = I: zero column of Y, T_ii = 0
+      // g[0:i] = Y[:, 0:i]^H v_i
+      for (int j = 0; j < i; ++j) {
+        cplx acc = 0.0;
+        for (int r = i; r < m1; ++r) acc += std::conj(B.Y[(size_t)r * nb + j]) * B.Y[(size_t)r * nb + i];
+        g[j] = acc;
+      }
+      for (int j = 0; j < i; ++j) {
+        cplx acc = 0.0;
+        for (int l = j; l < i; ++l) acc += B.T[(size_t)j * nb + l] * g[l];
+        B.T[(size_t)j * nb + i] = -2.0 * acc;
+      }
+      B.T[(size_t)i * nb + i] = 2.0;
+    }
+    blks.push_back(std::move(B));
+  }
   pool.run([&](int t, int nt) {
     int lo, hi;
     Pool::range(n, t, nt, lo, hi);
     if (lo >= hi) return;
-    const int w2 = 2 * (hi - lo);
-    std::vector<double> tv(w2);
-    for (int k = n - 3; k >= 0; --k) {
-      const auto& v = vs[k];
-      if (v.empty()) continue;
-      const int m = n - k - 1;
-      std::fill(tv.begin(), tv.end(), 0.0);               // t = v^H V_sub
-      for (int i = 0; i < m; ++i) {
-        const double cr = v[i].real(), ci = -v[i].imag();
-        const double* Vi = reinterpret_cast<const double*>(&V[(size_t)(k + 1 + i) * n + lo]);
-        for (int j = 0; j < w2; j += 2) {
-          tv[j] += cr * Vi[j] - ci * Vi[j + 1];
-          tv[j + 1] += cr * Vi[j + 1] + ci * Vi[j];
+    const int w = hi - lo, w2 = 2 * w;
+    std::vector<double> W((size_t)kWY * w2), W2((size_t)kWY * w2);
+    for (int bi = (int)blks.size() - 1; bi >= 0; --bi) {
+      const Blk& B = blks[bi];
+      const int nb = B.k2 - B.k1 + 1, m1 = n - B.k1 - 1, r0 = B.k1 + 1;
+      // W = Y^H V_sub (interleaved re, im)
+      std::fill(W.begin(), W.begin() + (size_t)nb * w2, 0.0);
+      for (int r = 0; r < m1; ++r) {
+        const double* __restrict__ Vr = reinterpret_cast<const double*>(&V[(size_t)(r0 + r) * n + lo]);
+        const cplx* Yr = &B.Y[(size_t)r * nb];
+        const int jmax = std::min(nb, r + 1);      // v_{k1+j} starts at row j of the block
+        for (int j = 0; j < jmax; ++j) {
+          const double yr = Yr[j].real(), yi = -Yr[j].imag();
+          double* __restrict__ Wj = &W[(size_t)j * w2];
+          for (int c = 0; c < w2; c += 2) {
+            Wj[c] += yr * Vr[c] - yi * Vr[c + 1];
+            Wj[c + 1] += yr * Vr[c + 1] + yi * Vr[c];
+          }
         }
       }
-      for (int i = 0; i < m; ++i) {
-        const double vr = 2.0 * v[i].real(), vim = 2.0 * v[i].imag();
-        double* Vi = reinterpret_cast<double*>(&V[(size_t)(k + 1 + i) * n + lo]);
-        for (int j = 0; j < w2; j += 2) {
-          Vi[j] -= vr * tv[j] - vim * tv[j + 1];
-          Vi[j + 1] -= vr * tv[j + 1] + vim * tv[j];
+      // W2 = T W
+      for (int j = 0; j < nb; ++j) {
+        double* __restrict__ W2j = &W2[(size_t)j * w2];
+        std::fill(W2j, W2j + w2, 0.0);
+        for (int l = j; l < nb; ++l) {
+          const double tr = B.T[(size_t)j * nb + l].real(), ti = B.T[(size_t)j * nb + l].imag();
+          const double* __restrict__ Wl = &W[(size_t)l * w2];
+          for (int c = 0; c < w2; c += 2) {
+            W2j[c] += tr * Wl[c] - ti * Wl[c + 1];
+            W2j[c + 1] += tr * Wl[c + 1] + ti * Wl[c];
+          }
+        }
+      }
+      // V_sub -= Y W2
+      for (int r = 0; r < m1; ++r) {
+        double* __restrict__ Vr = reinterpret_cast<double*>(&V[(size_t)(r0 + r) * n + lo]);
+        const cplx* Yr = &B.Y[(size_t)r * nb];
+        const int jmax = std::min(nb, r + 1);
+        for (int j = 0; j < jmax; ++j) {
+          const double yr = Yr[j].real(), yi = Yr[j].imag();
+          const double* __restrict__ W2j = &W2[(size_t)j * w2];
+          for (int c = 0; c < w2; c += 2) {
+            Vr[c] -= yr * W2j[c] - yi * W2j[c + 1];
+            Vr[c + 1] -= yr * W2j[c + 1] + yi * W2j[c];
+          }
         }
       }
     }
