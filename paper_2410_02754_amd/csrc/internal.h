@@ -206,6 +206,7 @@ struct chfsi_ctx {
   size_t nl_fixed_bytes = 0;
   chfsi::DevBuf<double> panel;                // row panel for in-place rotations
   chfsi::DevBuf<double> cd_partial;           // adjoint cross densities per column group
+  chfsi::DevBuf<int32_t> den_order;           // cell order of the density kernels (4x4x4 tiles)
   chfsi::DevBuf<double> ref_b1, ref_wq;       // 1-D interpolation table and weights (device copy)
   chfsi::DevBuf<double> occ;                  // occupations of the last density call (device copy)
   // form of the local operator: CHFSI_FORM_CELL_MATRIX (stored cell matrices)

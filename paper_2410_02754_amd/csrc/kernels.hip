@@ -903,118 +903,124 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
 }
 
 // Densities (one operand, two spins) with n_q = n_p: a workgroup of 512 threads
-// owns one cell and a group of columns and walks it in chunks of DC = 8 columns,
-// each chunk in two rounds (spin up, then spin down) of 8 LDS fields of n_p^3
-// values (44 KB at n_p = 7).  A round's z-line loads cover 8 consecutive
-// columns of one row, i.e. whole 128-byte lines, so a line is fetched once per
-// cell that holds the node; after the spin-up round each thread keeps the 8
-// spin-up values of its quadrature point in registers and combines them with
-// the spin-down round.  The next round's z-lines are loaded while the current
-// one runs its LDS phases.  Output as qfield_sf_kernel (wJ = 0: no weights).
-constexpr int kDenCols = 8;
+// owns one cell and one of n_groups interleaved column groups (group g takes the
+// chunks of DC = 4 columns g, g + n_groups, ...) and walks it chunk by chunk,
+// both spins at once (8 LDS fields of n_p^3 values, 44 KB at n_p = 7).  A
+// chunk's z-line loads cover 4 consecutive columns of a row, half a 128-byte
+// line: the group holding the other half is the neighbouring work item, which
+// runs at the same time on the same XCD, so each line is fetched once.
+// M^{-1/2} at the cell's nodes sits in LDS, so the kernel stays within 128
+// VGPRs at n_p <= 7 and two workgroups share a CU.  The LDS fields are padded
+// (den_px, den_fp: x extent and field gap per n_p) so that the eight lanes of
+// a 128-bit LDS access hit distinct banks in the line passes (at n_p = 7 the
+// compact layout puts two lanes of every eight on one bank in the y pass).  The next chunk's z-lines are
+// loaded while the current one runs its LDS phases (LDS-only barriers).  Work
+// item bid -> column group bid % n_groups, cell order[bid / n_groups] (4x4x4
+// tiles of cells, tile after tile; each XCD takes a contiguous range, so the
+// workgroups resident on an XCD hold a compact block of cells and their shared
+// face nodes meet in its L2).  Output as qfield_sf_kernel (no quadrature weights).
+constexpr int kDenCols = 4;
+constexpr int kDenTile = 4;
+constexpr int den_px(int NP) { return NP <= 3 ? NP : NP <= 6 ? 7 : 9; }
+constexpr int den_fp(int NP) {
+  return NP == 2 ? 1 : NP == 4 ? 1 : NP == 5 ? 6 : NP == 6 ? 11 : NP == 8 ? 1 : NP == 9 ? 6 : 0;
+}
+constexpr int den_field(int NP) { return den_px(NP) * NP * NP + den_fp(NP); }
 
 template <int NP>
 __global__ __launch_bounds__(kQfThreads) void density_sf_kernel(
     const double2* __restrict__ X, int64_t ldx, int n_vec, const int32_t* __restrict__ cell_nodes,
-    const double* __restrict__ minv_sqrt, const double* __restrict__ tab, int n_cells, int n_groups,
-    int cols_per_group, const double* __restrict__ colw, double* __restrict__ partial) {
-  constexpr int NT = kQfThreads, DC = kDenCols;
+    const int32_t* __restrict__ order, const double* __restrict__ minv_sqrt, const double* __restrict__ tab,
+    int n_cells, int n_groups, const double* __restrict__ colw, double* __restrict__ partial) {
+  constexpr int NT = kQfThreads, DC = kDenCols, NF = 2 * DC;
   constexpr int N2 = NP * NP, N3 = N2 * NP;
-  constexpr int NTASK = DC * N2, TPT = (NTASK + NT - 1) / NT;
+  constexpr int NTASK = NF * N2, TPT = (NTASK + NT - 1) / NT;
   constexpr int QPT = (N3 + NT - 1) / NT;
+  constexpr int SY = den_px(NP), SZ = SY * NP, SF = den_field(NP);
+  static_assert(SY >= NP && (NP - 1) * (1 + SY + SZ) < SF, "padded field layout overlaps");
   extern __shared__ double2 den_sm[];
-  double2* buf = den_sm;                // [DC][N3]
+  double2* buf = den_sm;                                    // [DC][2 spins][SF]
+  double* ssc = reinterpret_cast<double*>(buf + NF * SF);   // [N3] M^{-1/2} at the cell's nodes
   const double* eoBf = tab + 2 * N2 + NP;
   const int total = n_cells * n_groups;
   const int per_xcd = (total + 7) / 8;
   const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (bid >= total) return;
-  const int e = bid % n_cells, g = bid / n_cells, tid = threadIdx.x;
-  const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
+  const int g = bid % n_groups, e = order[bid / n_groups], tid = threadIdx.x;
+  const int c_end = n_vec, c_step = DC * n_groups;
   const int32_t* nodes = cell_nodes + (size_t)e * N3;
+  for (int i = tid; i < N3; i += NT) ssc[i] = minv_sqrt[nodes[i]];
 
-  // the thread's z-line tasks (column offset c fastest, then the line l)
+  // the thread's z-line tasks: column offset c fastest, then the spin, then the line
   int32_t nd[TPT][NP];
-  double sc[TPT][NP];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int t = min(tid + NT * k, NTASK - 1);
-    const int l = t / DC;
+    const int l = t / NF;
 #pragma unroll
-    for (int z = 0; z < NP; ++z) {
-      nd[k][z] = nodes[l + z * N2];
-      sc[k][z] = minv_sqrt[nd[k][z]];
-    }
+    for (int z = 0; z < NP; ++z) nd[k][z] = nodes[l + z * N2];
   }
-  auto zload = [&](int n0, int sp, double2 (&zv)[TPT][NP]) {
+  auto zload = [&](int n0, double2 (&zv)[TPT][NP]) {
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
       const int t = min(tid + NT * k, NTASK - 1);
       const int col = min(n0 + t % DC, c_end - 1);
+      const int sp = (t / DC) & 1;
 #pragma unroll
       for (int z = 0; z < NP; ++z) zv[k][z] = X[(2 * (int64_t)nd[k][z] + sp) * ldx + col];
     }
   };
   double2 zv[TPT][NP];
-  zload(c_begin, 0, zv);
+  zload(g * DC, zv);
   double acc[QPT][4];
-  double2 up[QPT][DC];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
-  for (int n0 = c_begin; n0 < c_end; n0 += DC) {
+  lds_barrier();                          // ssc is written
+  for (int n0 = g * DC; n0 < c_end; n0 += c_step) {
+    // z interpolation in registers (zero past the last column) into LDS
 #pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-      // z interpolation in registers (zero past the last column) into LDS
+    for (int k = 0; k < TPT; ++k) {
+      const int t = tid + NT * k;
+      if (t >= NTASK) break;
+      const int c = t % DC, sp = (t / DC) & 1, l = t / NF;
+      const bool ok = n0 + c < c_end;
+      double2 u[NP];
 #pragma unroll
-      for (int k = 0; k < TPT; ++k) {
-        const int t = tid + NT * k;
-        if (t >= NTASK) break;
-        const int c = t % DC, l = t / DC;
-        const bool ok = n0 + c < c_end;
-        double2 u[NP];
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          const double f = ok ? sc[k][i] : 0.0;
-          u[i] = double2{f * zv[k][i].x, f * zv[k][i].y};
-        }
-        double2* out = buf + c * N3 + l;
-        double2 r[NP];
-        sf_eo<double, NP, false>(eoBf, u, r);
-#pragma unroll
-        for (int o = 0; o < NP; ++o) out[o * N2] = r[o];
+      for (int i = 0; i < NP; ++i) {
+        const double f = ok ? ssc[l + i * N2] : 0.0;
+        u[i] = double2{f * zv[k][i].x, f * zv[k][i].y};
       }
-      // the next round's rows: spin down of this chunk, or spin up of the next
-      if (sp == 0) zload(n0, 1, zv);
-      else if (n0 + DC < c_end) zload(n0 + DC, 0, zv);
-      lds_barrier();
-      sf_line_pass<NP, DC, 1, NT>(eoBf, buf, buf);
-      lds_barrier();
-      sf_line_pass<NP, DC, 0, NT>(eoBf, buf, buf);
-      lds_barrier();
+      double2* out = buf + (2 * c + sp) * SF + (l % NP) + (l / NP) * SY;
+      double2 r[NP];
+      sf_eo<double, NP, false>(eoBf, u, r);
 #pragma unroll
-      for (int j = 0; j < QPT; ++j) {
-        const int q = tid + NT * j;
-        if (q >= N3) continue;
-        if (sp == 0) {
-#pragma unroll
-          for (int c = 0; c < DC; ++c) up[j][c] = buf[c * N3 + q];
-        } else {
-#pragma unroll
-          for (int c = 0; c < DC; ++c) {
-            const double cw = (n0 + c < c_end) ? (colw ? colw[n0 + c] : 1.0) : 0.0;
-            const double2 u0 = up[j][c], u1 = buf[c * N3 + q];
-            const double r00 = u0.x * u0.x + u0.y * u0.y;
-            const double r11 = u1.x * u1.x + u1.y * u1.y;
-            const double r01 = u0.x * u1.x + u0.y * u1.y, i01 = u0.x * u1.y - u0.y * u1.x;
-            acc[j][0] += cw * (r00 + r11);
-            acc[j][1] += cw * (2.0 * r01);       // u^H sigma_x u
-            acc[j][2] += cw * (2.0 * i01);       // u^H sigma_y u
-            acc[j][3] += cw * (r00 - r11);       // u^H sigma_z u
-          }
-        }
-      }
-      lds_barrier();   // the next round overwrites the buffer
+      for (int o = 0; o < NP; ++o) out[o * SZ] = r[o];
     }
+    if (n0 + c_step < c_end) zload(n0 + c_step, zv);
+    lds_barrier();
+    sf_line_pass<NP, NF, 1, NT, double, SY, SZ, SF>(eoBf, buf, buf);
+    lds_barrier();
+    sf_line_pass<NP, NF, 0, NT, double, SY, SZ, SF>(eoBf, buf, buf);
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+      const int q = tid + NT * j;
+      if (q >= N3) continue;
+      const int pq = (q % NP) + ((q / NP) % NP) * SY + (q / N2) * SZ;
+#pragma unroll
+      for (int c = 0; c < DC; ++c) {
+        const double cw = (n0 + c < c_end) ? (colw ? colw[n0 + c] : 1.0) : 0.0;
+        const double2 u0 = buf[(2 * c) * SF + pq], u1 = buf[(2 * c + 1) * SF + pq];
+        const double r00 = u0.x * u0.x + u0.y * u0.y;
+        const double r11 = u1.x * u1.x + u1.y * u1.y;
+        const double r01 = u0.x * u1.x + u0.y * u1.y, i01 = u0.x * u1.y - u0.y * u1.x;
+        acc[j][0] += cw * (r00 + r11);
+        acc[j][1] += cw * (2.0 * r01);       // u^H sigma_x u
+        acc[j][2] += cw * (2.0 * i01);       // u^H sigma_y u
+        acc[j][3] += cw * (r00 - r11);       // u^H sigma_z u
+      }
+    }
+    lds_barrier();   // the next round overwrites the buffer
   }
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
@@ -1026,25 +1032,47 @@ __global__ __launch_bounds__(kQfThreads) void density_sf_kernel(
   }
 }
 
+// The cell order of density_sf_kernel: tiles of kDenTile^3 cells (ragged at
+// the edges), tile after tile, cells within a tile x fastest.
+static void den_order_prepare(chfsi_ctx* c) {
+  if (c->den_order.ptr && c->den_order.n == (size_t)c->n_cells) return;
+  constexpr int T = kDenTile;
+  std::vector<int32_t> ord;
+  ord.reserve(c->n_cells);
+  const int nx = c->nc[0], ny = c->nc[1], nz = c->nc[2];
+  for (int tz = 0; tz < nz; tz += T)
+    for (int ty = 0; ty < ny; ty += T)
+      for (int tx = 0; tx < nx; tx += T)
+        for (int z = tz; z < std::min(nz, tz + T); ++z)
+          for (int y = ty; y < std::min(ny, ty + T); ++y)
+            for (int x = tx; x < std::min(nx, tx + T); ++x) ord.push_back(x + nx * (y + ny * z));
+  CHFSI_CHECK((int64_t)ord.size() == c->n_cells, CHFSI_EINVAL, "densities: cell order does not cover the mesh");
+  c->den_order.release();
+  c->den_order.upload(ord.data(), ord.size(), c->stream);
+  CHFSI_HIP(hipStreamSynchronize(c->stream));   // the host vector ends here
+}
+
 template <int NP>
 static void launch_density_sf(chfsi_ctx* c, const double2* X, int64_t ldx, int n_vec, const double* colw,
                               double* rho, double* mag) {
   constexpr int DC = kDenCols;
-  const size_t sh = (size_t)DC * NP * NP * NP * sizeof(double2);
+  constexpr int N3 = NP * NP * NP;
+  const size_t sh = (size_t)2 * DC * den_field(NP) * sizeof(double2) + (size_t)N3 * sizeof(double);
   if (c->mf_tab.n == 0) mf_prepare(c);
-  const int max_groups = std::max(1, cdiv(n_vec, DC));
-  const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
-  int groups = std::min(max_groups, want);
-  const int cpg = DC * cdiv(cdiv(n_vec, groups), DC);
-  groups = cdiv(n_vec, cpg);
+  den_order_prepare(c);
+  // at least two groups (the two halves of each 128-byte row line), more on
+  // small meshes to fill the GPU; every group holds at least one chunk
+  const int n_chunks = cdiv(n_vec, DC);
+  const int want = std::max(2, cdiv(4096, std::max(1, c->n_cells)));
+  const int groups = std::max(1, std::min(n_chunks, want));
   const int64_t n_points = (int64_t)c->n_cells * c->nq3;
   c->cd_partial.alloc((size_t)groups * n_points * 4);
   const int64_t total = (int64_t)c->n_cells * groups;
   CHFSI_CHECK(total < (int64_t)1 << 30, CHFSI_EINVAL, "densities: too many work items");
   StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, (double)c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
   hipLaunchKernelGGL((density_sf_kernel<NP>), dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kQfThreads), sh,
-                     c->stream, X, ldx, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->mf_tab.ptr, c->n_cells,
-                     groups, cpg, colw, c->cd_partial.ptr);
+                     c->stream, X, ldx, n_vec, c->cell_nodes.ptr, c->den_order.ptr, c->minv_sqrt.ptr,
+                     c->mf_tab.ptr, c->n_cells, groups, colw, c->cd_partial.ptr);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
                      dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, 1.0, rho, mag);

@@ -105,21 +105,36 @@ __device__ __forceinline__ void sf_eo(const T* __restrict__ tb, const typename S
   }
 }
 
+// First point of line l along DIM in a padded field (point (x, y, z) at
+// x + SY y + SZ z).
+template <int NP, int DIM, int SY, int SZ>
+__device__ __forceinline__ int sf_line_base_padded(int l) {
+  if constexpr (DIM == 0) return (l % NP) * SY + (l / NP) * SZ;    // l = y + NP z
+  else if constexpr (DIM == 1) return (l % NP) + (l / NP) * SZ;    // l = x + NP z
+  else return (l % NP) + (l / NP) * SY;                             // l = x + NP y
+}
+
 // out = contraction of fields 0..NF-1 along DIM with a centrosymmetric n_p x n_p
 // matrix given by its even-odd table (sf_eo):
 //   B (nodes -> points):  out[.. o ..] = sum_i B[i][o] in[.. i ..]
 //   B^T (points -> nodes): out[.. o ..] = sum_i B[o][i] in[.. i ..]
 // in and out may be the same buffer: a thread reads its whole line before it
-// writes it, and the lines of one pass are disjoint.
-template <int NP, int NF, int DIM, int NT = 256, class T = double>
+// writes it, and the lines of one pass are disjoint.  Fields are compact
+// (point (x, y, z) at x + NP y + NP^2 z, fields NP^3 apart) unless SY, SZ, SF
+// give a padded layout: point at x + SY y + SZ z, fields SF apart.
+template <int NP, int NF, int DIM, int NT = 256, class T = double, int SY = NP, int SZ = NP * NP,
+          int SF = NP * NP * NP>
 __device__ __forceinline__ void sf_line_pass(const T* __restrict__ eo, const typename SfC2<T>::type* in,
                                              typename SfC2<T>::type* out) {
   typedef typename SfC2<T>::type C2;
-  constexpr int N2 = NP * NP, N3 = N2 * NP;
-  constexpr int S = DIM == 0 ? 1 : DIM == 1 ? NP : N2;
+  constexpr int N2 = NP * NP;
+  constexpr bool compact = SY == NP && SZ == N2;
+  constexpr int S = DIM == 0 ? 1 : DIM == 1 ? SY : SZ;
   for (int t = threadIdx.x; t < N2 * NF; t += NT) {
     const int l = t % N2, f = t / N2;
-    const int base = f * N3 + sf_line_base<NP, DIM>(l);
+    int base;
+    if constexpr (compact) base = f * SF + sf_line_base<NP, DIM>(l);
+    else base = f * SF + sf_line_base_padded<NP, DIM, SY, SZ>(l);
     C2 v[NP], r[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) v[j] = in[base + j * S];

@@ -1,6 +1,7 @@
 """GPU densities (eqn:rho, eqn:mag) through the C ABI, against the oracle's
 plain definition on small systems (several column groups, ragged column tails,
-p = 3 .. 8 with up to 10^3 quadrature points per cell), against properties
+p = 3 .. 8 with up to 10^3 quadrature points per cell, and the sum-factorised
+kernel at every order p = 1 .. 8 with n_q = p + 1), against properties
 that hold at any size (GLL charge integral, |m| <= rho, additivity over
 blocks, run-to-run identity), and on sampled cells of the large workload
 (20^3 cells, p = 6, 512 columns, Fermi-Dirac occupations at 500 K)."""
@@ -57,6 +58,35 @@ def test_density_matches_oracle(name, kw, n_vec):
     scale = np.abs(rho_o).max()
     er, em = np.abs(r - rho_o).max() / scale, np.abs(m - m_o).max() / scale
     print(f"[density {name}] n_vec {n_vec}: rel err rho {er:.2e} m {em:.2e}", flush=True)
+    assert er < 1e-13 and em < 1e-13
+    op.close()
+
+
+SF_CASES = [(p, (2, 2, 2)) for p in range(1, 9)] + [(1, (16, 16, 16)), (2, (16, 16, 16))]
+
+
+@pytest.mark.parametrize("p,nc", SF_CASES, ids=[f"p{c[0]}_{c[1][0]}x{c[1][1]}x{c[1][2]}" for c in SF_CASES])
+def test_density_quadrature_point_kernel_every_order(p, nc):
+    """n_q = p + 1 (the sum-factorised kernel, one padded LDS layout per order):
+    every order p = 1..8 against the oracle's definition, 13 or 21 columns in
+    chunks of 4 (ragged last chunk); on the 16^3-cell meshes each column group
+    walks several chunks (the prefetch path)."""
+    nv = 21 if nc[0] == 16 else 13
+    s = synth.make_system("dsf", n_cells=nc, box=tuple(1.5 * c for c in nc), p=p, n_atoms=1, lmax=1,
+                          rcut_sigmas=5.0, n_vec=nv)
+    assert s.n_q == p + 1
+    mesh = ham.mesh_for(s)
+    MD = mesh.lumped_mass()
+    X0 = synth.random_block(7, s.n_dof, nv)
+    f = np.linspace(1.0, 0.1, nv)
+    rho_o, m_o = od.density_magnetisation(mesh, MD, X0, f)
+    op = _op(s)
+    rho, mag = _fields(op)
+    op.density(torch.tensor(X0, device="cuda"), f, rho, mag)
+    r, m = rho.cpu().numpy(), mag.cpu().numpy()
+    scale = np.abs(rho_o).max()
+    er, em = np.abs(r - rho_o).max() / scale, np.abs(m - m_o).max() / scale
+    print(f"[density sf p{p} {nc}] rel err rho {er:.2e} m {em:.2e}", flush=True)
     assert er < 1e-13 and em < 1e-13
     op.close()
 
