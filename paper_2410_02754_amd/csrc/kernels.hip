@@ -781,8 +781,11 @@ __global__ void cross_density_reduce_kernel(const double* __restrict__ partial, 
 // along z there, and the y and x passes run in place in LDS; the next chunk's
 // z-lines are loaded while the current chunk runs its LDS phases (LDS-only
 // barriers).  tab = the matrix-free tables [B][Dq][w][even-odd tables].
-// Work item bid -> cell bid % n_cells, column group bid / n_cells, neighbouring
-// cells (which share face nodes) on one XCD.
+// The n_groups column groups are interleaved (group g takes the chunks g,
+// g + n_groups, ...) and n_groups is a multiple of the chunks that share a
+// 128-byte row line, so the groups of one cell, neighbouring work items on one
+// XCD, read the pieces of each line at the same time.  Work item bid -> column
+// group bid % n_groups, cell order[bid / n_groups] (the densities' tiled order).
 constexpr int kQfThreads = 512;
 constexpr int qf_fields(int) { return 8; }
 
@@ -790,8 +793,8 @@ template <int NP, int NS>
 __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
     const double2* __restrict__ L, int64_t ldl, const double2* __restrict__ Y, int64_t ldy, int n_vec,
     const int32_t* __restrict__ cell_nodes, const double* __restrict__ minv_sqrt, const double* __restrict__ tab,
-    double J, int n_cells, int n_groups, int cols_per_group, const double* __restrict__ colw, int wJ,
-    double* __restrict__ partial) {
+    double J, int n_cells, int n_groups, const int32_t* __restrict__ order, const double* __restrict__ colw,
+    int wJ, double* __restrict__ partial) {
   constexpr int NT = kQfThreads;
   constexpr int NF = qf_fields(NP), CW = NF / NS;
   constexpr int N2 = NP * NP, N3 = N2 * NP;
@@ -805,8 +808,8 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
   const int per_xcd = (total + 7) / 8;
   const int bid = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (bid >= total) return;
-  const int e = bid % n_cells, g = bid / n_cells, tid = threadIdx.x;
-  const int c_begin = g * cols_per_group, c_end = min(n_vec, c_begin + cols_per_group);
+  const int g = bid % n_groups, e = order[bid / n_groups], tid = threadIdx.x;
+  const int c_end = n_vec, c_step = CW * n_groups;
   const int32_t* nodes = cell_nodes + (size_t)e * N3;
 
   // the thread's tasks: (column offset c, stream s = 2 operand + spin, z-line l);
@@ -831,12 +834,12 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
 #pragma unroll
   for (int k = 0; k < TPT; ++k)
 #pragma unroll
-    for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(c_begin + tcol[k], c_end - 1)];
+    for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(g * CW + tcol[k], c_end - 1)];
 
   double acc[QPT][4];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
-  for (int n0 = c_begin; n0 < c_end; n0 += CW) {
+  for (int n0 = g * CW; n0 < c_end; n0 += c_step) {
     double cwv[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) cwv[c] = (n0 + c < c_end) ? (colw ? colw[n0 + c] : 1.0) : 0.0;
@@ -859,11 +862,11 @@ __global__ __launch_bounds__(kQfThreads) void qfield_sf_kernel(
 #pragma unroll
       for (int o = 0; o < NP; ++o) out[o * N2] = r[o];
     }
-    if (n0 + CW < c_end) {
+    if (n0 + c_step < c_end) {
 #pragma unroll
       for (int k = 0; k < TPT; ++k)
 #pragma unroll
-        for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(n0 + CW + tcol[k], c_end - 1)];
+        for (int z = 0; z < NP; ++z) zv[k][z] = row[k][z][min(n0 + c_step + tcol[k], c_end - 1)];
     }
     lds_barrier();
     sf_line_pass<NP, NF, 1, NT>(eoBf, buf, buf);
@@ -1085,11 +1088,13 @@ static void launch_qfield_sf(chfsi_ctx* c, const double2* L, int64_t ldl, const 
   constexpr int CW = qf_fields(NP) / NS;
   const size_t sh = (size_t)qf_fields(NP) * NP * NP * NP * sizeof(double2);
   if (c->mf_tab.n == 0) mf_prepare(c);
-  const int max_groups = std::max(1, cdiv(n_vec, CW));
-  const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
-  int groups = std::min(max_groups, want);
-  const int cpg = CW * cdiv(cdiv(n_vec, groups), CW);
-  groups = cdiv(n_vec, cpg);
+  den_order_prepare(c);
+  // a multiple of the chunks that share a 128-byte row line (8 complex values),
+  // at least 4096 work items where the columns allow; each group holds a chunk
+  constexpr int LQ = 8 / CW > 1 ? 8 / CW : 1;
+  const int n_chunks = cdiv(n_vec, CW);
+  const int want = LQ * cdiv(std::max(1, cdiv(4096, std::max(1, c->n_cells))), LQ);
+  const int groups = std::max(1, std::min(n_chunks, want));
   const int64_t n_points = (int64_t)c->n_cells * c->nq3;
   c->cd_partial.alloc((size_t)groups * n_points * 4);
   const int64_t total = (int64_t)c->n_cells * groups;
@@ -1097,7 +1102,7 @@ static void launch_qfield_sf(chfsi_ctx* c, const double2* L, int64_t ldl, const 
   StageTimer tm(c, CHFSI_STAGE_AXPY, 0.0, 0.0, (double)NS / 2 * c->n_cells * c->nloc * 2.0 * n_vec * sizeof(double2));
   hipLaunchKernelGGL((qfield_sf_kernel<NP, NS>), dim3((unsigned)(8 * ((total + 7) / 8))), dim3(kQfThreads), sh,
                      c->stream, L, ldl, Y, ldy, n_vec, c->cell_nodes.ptr, c->minv_sqrt.ptr, c->mf_tab.ptr, c->J,
-                     c->n_cells, groups, cpg, colw, wJ, c->cd_partial.ptr);
+                     c->n_cells, groups, c->den_order.ptr, colw, wJ, c->cd_partial.ptr);
   LAUNCH_CHECK();
   hipLaunchKernelGGL(cross_density_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n_points, 256), 4096)),
                      dim3(256), 0, c->stream, c->cd_partial.ptr, n_points, groups, alpha, dV, dB);
