@@ -371,7 +371,8 @@ def bench_scf(args, torch, n_iter=3):
     CholGS, Rayleigh-Ritz), then one Fermi level, the densities of all k-points, the
     field solves and the mixing.  Timed: n_iter iterations restarted from the state of
     a two-iteration warm-up (the first timed iteration also orthonormalises the given
-    blocks), FP64 and mixed precision (the loop's residual form of the filter); the
+    blocks), FP64 and mixed precision (the loop's residual form of the filter), with the
+    stored cell matrices (the JSON value) and then with the matrix-free operator; the
     oracle's SCF iteration on a small k-sampled system is timed on the host."""
     import synth
     from paper_2410_02754_amd import scf_run
@@ -409,7 +410,11 @@ def bench_scf(args, torch, n_iter=3):
     torch.cuda.synchronize()
     log(f"[bench] scf warm-up (2 iterations): {time.perf_counter() - t0:.1f} s")
     X_w, rho_w, m_w = X.clone(), rho.clone(), m.clone()
-    for prec in (("fp64",) if args.no_mixed else ("fp64", "mixed")):
+    runs = [(form, prec) for form in ("cell", "matrix_free")
+            for prec in (("fp64",) if args.no_mixed else ("fp64", "mixed"))]
+    for form, prec in runs:
+        if form != op.form:
+            op.set_form(form)            # scf_run sets the local operator in every iteration
         res = {}
         for label, iters in (("timed", n_iter),):
             X.copy_(X_w)
@@ -433,9 +438,17 @@ def bench_scf(args, torch, n_iter=3):
                        "residual_norms": [float(f"{h['resid']:.3e}") for h in hist],
                        "mu_Ha": hist[-1]["mu"], "theta0_Ha": hist[-1]["theta0"],
                        "hartree_cg_steps": [h["hartree_iters"] for h in hist]}
-                log(f"[bench] scf {prec}: {dt / iters:.3f} s per iteration, residuals "
+                log(f"[bench] scf {form} {prec}: {dt / iters:.3f} s per iteration, residuals "
                     + " ".join(f"{h['resid']:.2e}" for h in hist))
-        out[prec if prec == "fp64" else "mixed_resid"] = res
+        key = prec if prec == "fp64" else "mixed_resid"
+        if form == "cell":
+            out[key] = res
+        else:
+            mf = out.setdefault("matrix_free", {"form": "matrix-free local operator (sum factorisation), "
+                                                        "same restart state"})
+            mf[key] = res
+            mf[key]["speedup_vs_cell_fp64"] = round(out["fp64"]["s_per_iteration"] / res["s_per_iteration"], 3)
+            mf[key]["max_rel_diff_residuals_vs_cell"] = float(f"{max(abs(a - b) / abs(b) for a, b in zip(res['residual_norms'], out[key]['residual_norms'])):.1e}")
     out["value"] = out["fp64"]["s_per_iteration"]
     out["ms_per_step"] = round(1e3 * out["value"], 1)
     if "mixed_resid" in out:

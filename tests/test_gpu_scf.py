@@ -181,13 +181,15 @@ def test_scf_uniform_gas_matches_oracle_and_closed_form():
     op.close()
 
 
-@pytest.mark.parametrize("form", ["cell"])
-def test_scf_two_grid_with_atoms_matches_oracle(form):
+@pytest.mark.parametrize("form,nq", [("cell", 5), ("matrix_free", 4)])
+def test_scf_two_grid_with_atoms_matches_oracle(form, nq):
+    """The two grids share the quadrature points; with the matrix-free operator on
+    the fine grid (n_q = p + 1 = 4) the coarse grid keeps its cell matrices."""
     from paper_2410_02754_amd import scf_run
     kw_sys = dict(n_cells=(2, 2, 2), box=(5.0, 5.0, 5.0), n_atoms=2, lmax=1, rcut_sigmas=5.0, n_vec=10,
                   degree=8, seed=6)
-    fine = synth.make_system("scf", p=3, n_q=5, **kw_sys)
-    coarse = synth.make_system("scf", p=2, n_q=5, **kw_sys)
+    fine = synth.make_system("scf", p=3, n_q=nq, **kw_sys)
+    coarse = synth.make_system("scf", p=2, n_q=nq, **kw_sys)
     mesh = ham.mesh_for(fine)
     pts = mesh.all_quad_points().reshape(-1, 3)
     E, nq3 = mesh.n_cell_total, mesh.nq ** 3
@@ -198,8 +200,8 @@ def test_scf_two_grid_with_atoms_matches_oracle(form):
     m0 = 0.2 * bext / 0.1 * rho0[..., None]
     kw = dict(passes_first=5, passes=2, depth=5, alpha=0.5, k0=0.8, tol=1e-7, tol_coarse=1e-2, max_iter=60)
     out = scf.scf(fine, vext, bext, rho0, m0, n_e, kT, coarse_system=coarse, **kw)
-    of = _op(fine.n_cells, fine.box, 3, 5, fine.atoms, form)
-    oc = _op(coarse.n_cells, coarse.box, 2, 5, coarse.atoms, form)
+    of = _op(fine.n_cells, fine.box, 3, nq, fine.atoms, form)
+    oc = _op(coarse.n_cells, coarse.box, 2, nq, coarse.atoms, "cell")
     rho, m = _dev(rho0), _dev(m0)
     ro, mo = torch.empty_like(rho), torch.empty_like(m)
     X = torch.empty((of.n_dof, 10), dtype=torch.complex128, device="cuda")
