@@ -419,6 +419,9 @@ typedef struct {
  * with sum_k w_k sum_n f_nk = N_e (chfsi_fermi_dirac with weights w_k), and the
  * output densities are sum_k w_k sum_n f_nk |u_nk|^2 (likewise m).  The start
  * block of k-point ik is the chfsi_fill_random stream of seed + 7919 ik.
+ * The host eigensolve of each k-point's last Rayleigh-Ritz runs on a helper
+ * thread while the next k-point's work is issued (the results are those of
+ * the plain order); the call returns after that thread has finished.
  * In/out: rho_d, m_d hold the initial input densities and, on return, the last
  * input; rho_out_d, m_out_d the last output; X_d (fine grid) the last Ritz
  * blocks, block ik [2M][ldx] at X_d + ik 2M ldx complex entries; theta_h and

@@ -52,6 +52,17 @@ static void require_operator(const chfsi_ctx* c) {
   CHFSI_CHECK(c->have_local, CHFSI_ESTATE, "chfsi_set_local has not been called");
 }
 
+namespace chfsi {
+void rr_project(chfsi_ctx* c, int ik, const double2* X, int64_t ldx, double2* work, int64_t ldw, int n_vec,
+                std::vector<cplx>& Hp) {
+  KPoint& kp = kpoint(c, ik);
+  apply_H(c, kp, X, ldx, work, ldw, n_vec, CHFSI_PREC_FP64, 1.0, 0.0, 0.0);
+  gram(c, X, ldx, work, ldw, 2 * c->n_nodes, n_vec, Hp, true);
+  for (const auto& v : Hp)
+    CHFSI_CHECK(std::isfinite(v.real()) && std::isfinite(v.imag()), CHFSI_ENONFINITE, "projected H has NaN/Inf");
+}
+}  // namespace chfsi
+
 
 extern "C" {
 
@@ -479,6 +490,7 @@ size_t chfsi_workspace_bytes(const chfsi_ctx* c, int ik, int n_vec, int op) {
   }
 }
 
+
 int chfsi_rayleigh_ritz(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, int64_t ldw, int n_vec,
                         double* ritz, double* resid) {
   if (!c) return CHFSI_EINVAL;
@@ -488,13 +500,9 @@ int chfsi_rayleigh_ritz(chfsi_ctx* c, int ik, void* X, int64_t ldx, void* work, 
   check_block(c, work, ldw, n_vec, "work");
   CHFSI_CHECK(ritz != nullptr, CHFSI_EINVAL, "ritz_h must be non-NULL");
   CHFSI_CHECK(X != work, CHFSI_EINVAL, "X and work must be distinct");
-  KPoint& kp = kpoint(c, ik);
   const int64_t rows = 2 * c->n_nodes;
-  apply_H(c, kp, (const double2*)X, ldx, (double2*)work, ldw, n_vec, CHFSI_PREC_FP64, 1.0, 0.0, 0.0);
   std::vector<cplx> Hp;
-  gram(c, (const double2*)X, ldx, (const double2*)work, ldw, rows, n_vec, Hp, true);
-  for (const auto& v : Hp)
-    CHFSI_CHECK(std::isfinite(v.real()) && std::isfinite(v.imag()), CHFSI_ENONFINITE, "projected H has NaN/Inf");
+  rr_project(c, ik, (const double2*)X, ldx, (double2*)work, ldw, n_vec, Hp);
   std::vector<double> w;
   std::vector<cplx> Q;
   auto t0 = std::chrono::steady_clock::now();

@@ -294,6 +294,11 @@ void gram(chfsi_ctx* c, const double2* X, int64_t ldx, const double2* Y, int64_t
           int n, std::vector<cplx>& S, bool lower_only);
 void rotate_inplace(chfsi_ctx* c, double2* X, int64_t ldx, int64_t rows, int n,
                     const std::vector<cplx>& Q, bool upper_triangular);
+// Rayleigh-Ritz, first half: work = H X (FP64) and the projected matrix
+// Hp = X^H work (n x n, host, lower half); the caller solves it (hermitian_eig)
+// and rotates X by the eigenvectors (rotate_inplace), possibly later.
+void rr_project(chfsi_ctx* c, int ik, const double2* X, int64_t ldx, double2* work, int64_t ldw, int n_vec,
+                std::vector<cplx>& Hp);
 void column_resid_norms(chfsi_ctx* c, const double2* W, int64_t ldw, const double2* X, int64_t ldx,
                         int64_t rows, int n, const double* theta, double* out);
 double dot_re(chfsi_ctx* c, const double2* x, const double2* y, int64_t rows);

@@ -7,7 +7,9 @@
 // block operation runs on the device; the host keeps the loop, the Anderson
 // normal equations (depth x depth) and the occupations.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <future>
 #include <vector>
 
 #include "internal.h"
@@ -45,6 +47,46 @@ void check_rc(int rc, chfsi_ctx* c, const char* what) {
   if (rc != CHFSI_OK)
     throw Error{rc, std::string(what) + ": " + (c ? c->last_error : std::string(chfsi_last_error(nullptr)))};
 }
+
+// Rayleigh-Ritz of a k-point's last pass with its host eigensolve on a helper
+// thread: start() issues H X and the projected matrix (returning once that
+// matrix is on the host) and hands it to the thread; the caller goes on with
+// the next k-point's bound, filter and CholGS on the GPU; finish() takes the
+// eigenpairs, rotates the block and stores the Ritz values.  Nothing between
+// start() and finish() reads the block or the Ritz values of that k-point, and
+// the rotation needs no H X (no residual norms here).
+struct DeferredRR {
+  chfsi_ctx* g = nullptr;
+  void* X = nullptr;
+  int64_t ldx = 0;
+  int n = 0;
+  double* theta = nullptr;
+  std::vector<cplx> Hp, Q;
+  std::vector<double> w;
+  double ms = 0.0;
+  std::future<void> job;        // last member: waited for before the vectors go
+
+  void start(chfsi_ctx* ctx, int ik, void* Xb, int64_t ld, void* work, int64_t ldw, int nv, double* th) {
+    g = ctx;
+    X = Xb;
+    ldx = ld;
+    n = nv;
+    theta = th;
+    rr_project(g, ik, (const double2*)X, ldx, (double2*)work, ldw, n, Hp);
+    job = std::async(std::launch::async, [this]() {
+      const auto t0 = std::chrono::steady_clock::now();
+      hermitian_eig(Hp, n, w, Q);
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    });
+  }
+  void finish() {
+    if (!job.valid()) return;
+    job.get();                  // rethrows a failure of the eigensolve
+    stats_add_host(g, CHFSI_STAGE_HOST_DENSE, ms);
+    rotate_inplace(g, (double2*)X, ldx, 2 * g->n_nodes, n, Q, false);
+    for (int i = 0; i < n; ++i) theta[i] = w[i];
+  }
+};
 
 }  // namespace
 
@@ -251,6 +293,7 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
     v0.alloc((size_t)2 * fine->n_nodes);
     // per k-point: Ritz values and occupations; occupations times weights
     std::vector<double> theta((size_t)nk * N), occ((size_t)nk * N), wts((size_t)nk * N), occw(N), rnorm(N);
+    DeferredRR rr_late;
     for (int ik = 0; ik < nk; ++ik)
       for (int n = 0; n < N; ++n) wts[(size_t)ik * N + n] = wk[ik];
     int nh = 0, it = 0;
@@ -325,16 +368,24 @@ int chfsi_scf_run(chfsi_ctx* fine, chfsi_ctx* coarse, const chfsi_scf_params* pr
                        "scf_run: filter");
             int bad = -1;
             check_rc(chfsi_chol_gs(g, Xg, ldg, N, &bad), g, "scf_run: CholGS");
-            if (resid_form) {
-              // H X of the rotated block into R, then R = H X - X diag(theta)
+            if (p + 1 < npass && resid_form) {
+              // the next pass filters with R of the rotated block: H X into R, then
+              // R = H X - X diag(theta)
               check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Rg, N, N, th, rnorm.data()), g, "scf_run: RR");
               check_rc(chfsi_ritz_residual(g, Xg, ldg, Rg, N, N, th), g, "scf_run: residuals");
-            } else {
+            } else if (p + 1 < npass) {
               // residual norms are not needed here: no rotation of H X
               check_rc(chfsi_rayleigh_ritz(g, ik, Xg, ldg, Wg, wcols, N, th, nullptr), g, "scf_run: RR");
+            } else {
+              // last pass of this k-point (in the residual form R is formed again
+              // from the next iteration's operator): the eigensolve overlaps the
+              // next k-point's GPU work
+              rr_late.finish();
+              rr_late.start(g, ik, Xg, ldg, Wg, wcols, N, th);
             }
           }
         }
+        rr_late.finish();
         first = false;
         // one Fermi level for all (n, k); densities summed with the weights
         double mu = 0.0;
