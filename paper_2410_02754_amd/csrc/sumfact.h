@@ -14,7 +14,7 @@ namespace chfsi {
 
 // columns per workgroup of the matrix-free operator (2 fields per column: the
 // spins) for two LDS buffers of about 44 KB, so that three workgroups share a CU
-constexpr int sf_cols(int NP) { return NP <= 4 ? 8 : NP == 5 ? 4 : NP == 6 ? 3 : NP == 7 ? 2 : 1; }
+constexpr int sf_cols(int NP) { return NP <= 4 ? 8 : NP == 5 ? 4 : NP <= 7 ? 2 : 1; }
 
 // Workgroup barrier for LDS hand-offs: waits for this wave's LDS operations
 // only, so global loads issued before it (a prefetch of the next work item) stay
