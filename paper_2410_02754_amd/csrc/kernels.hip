@@ -101,7 +101,12 @@ constexpr int nl_col_blocks() { return sizeof(T) == 8 ? 1 : 2; }
 // used), k = four support entries per step, column = 16 of the tile's columns;
 // sixteen entries' operands are loaded before their MFMAs are issued.
 // REALP: the projector values are real (Gamma point), two real MFMAs per step.
-template <class T, bool REALP>
+// PACK (FP64, complex values, n_pj <= 8): rows 0-7 carry the real parts and
+// rows 8-15 the imaginary parts of the projectors, so one MFMA against Re x
+// and one against Im x replace the four of the plain complex step; row chi and
+// row chi + 8 sit in the same lane (accumulator registers j and j + 2), where
+//   Re c = (p_r x_r)[chi] + (p_i x_i)[chi + 8],  Im c = (p_r x_i)[chi] - (p_i x_r)[chi + 8].
+template <class T, bool REALP, bool PACK = false>
 __global__ __launch_bounds__(256) void nl_contract_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ sup_node,
     const int32_t* __restrict__ chunk_atom, const int32_t* __restrict__ chunk_begin,
@@ -110,6 +115,7 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
     const double2* __restrict__ X, int64_t ldx, int n_vec, typename C2<T>::type* __restrict__ partial) {
   typedef typename C2<T>::type CT;
   typedef typename Vec4<T>::type V4;
+  static_assert(!PACK || (!REALP && sizeof(T) == 8), "packed rows: FP64 complex projectors only");
   constexpr int U = 4;                    // k-steps per batch
   constexpr int NCB = nl_col_blocks<T>();
   // each XCD takes a contiguous range of the (window, atom)-ordered chunks, so the
@@ -124,7 +130,8 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
   const int ch = chunk_order[oi];
   const int a = chunk_atom[ch], b = chunk_begin[ch], e = chunk_end[ch];
   const int npj = atom_npj[a];
-  const bool rv = il < npj;               // this lane's A row is a projector in use
+  const int chi = PACK ? (il & 7) : il;   // projector of this lane's A row
+  const bool rv = chi < npj;              // ... and whether it is in use
   int col[NCB];
   bool cv[NCB];
 #pragma unroll
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
       const int j = j0 + 4 * u + kl;      // entry of this lane's k index
       const bool jv = j < e;
       const int64_t nd = sup_node[jv ? j : b];
-      pv[u] = (jv && rv) ? proj[(size_t)j * max_pj + il] : CT{(T)0, (T)0};
+      pv[u] = (jv && rv) ? proj[(size_t)j * max_pj + chi] : CT{(T)0, (T)0};
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
@@ -157,22 +164,33 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const T pr = pv[u].x, pi = pv[u].y, npi = -pv[u].y;
+      if constexpr (PACK) {
+        const T av = il < 8 ? pv[u].x : pv[u].y;
 #pragma unroll
-      for (int sp = 0; sp < 2; ++sp)
+        for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const T xr = (T)xv[u][sp][cb].x, xi = (T)xv[u][sp][cb].y;
-          cr[sp][cb] = mfma(pr, xr, cr[sp][cb]);      // conj(p) x
-          if (!REALP) cr[sp][cb] = mfma(pi, xi, cr[sp][cb]);
-          ci[sp][cb] = mfma(pr, xi, ci[sp][cb]);
-          if (!REALP) ci[sp][cb] = mfma(npi, xr, ci[sp][cb]);
-        }
+          for (int cb = 0; cb < NCB; ++cb) {
+            cr[sp][cb] = mfma(av, (T)xv[u][sp][cb].x, cr[sp][cb]);   // [p_r; p_i] x_r
+            ci[sp][cb] = mfma(av, (T)xv[u][sp][cb].y, ci[sp][cb]);   // [p_r; p_i] x_i
+          }
+      } else {
+        const T pr = pv[u].x, pi = pv[u].y, npi = -pv[u].y;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            const T xr = (T)xv[u][sp][cb].x, xi = (T)xv[u][sp][cb].y;
+            cr[sp][cb] = mfma(pr, xr, cr[sp][cb]);      // conj(p) x
+            if (!REALP) cr[sp][cb] = mfma(pi, xi, cr[sp][cb]);
+            ci[sp][cb] = mfma(pr, xi, ci[sp][cb]);
+            if (!REALP) ci[sp][cb] = mfma(npi, xr, ci[sp][cb]);
+          }
+      }
     }
   }
   CT* out = partial + (size_t)ch * 2 * max_pj * n_vec;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < (PACK ? 2 : 4); ++j) {
     const int x = acc_row<T>(lane, j);
     if (x >= npj) continue;
 #pragma unroll
@@ -181,8 +199,13 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) {
         CT v;
-        v.x = cr[sp][cb][j];
-        v.y = ci[sp][cb][j];
+        if constexpr (PACK) {
+          v.x = cr[sp][cb][j] + ci[sp][cb][j + 2];
+          v.y = ci[sp][cb][j] - cr[sp][cb][j + 2];
+        } else {
+          v.x = cr[sp][cb][j];
+          v.y = ci[sp][cb][j];
+        }
         out[(size_t)(2 * x + sp) * n_vec + col[cb]] = v;
       }
     }
@@ -442,6 +465,12 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
 // device array [n_atoms][2 max_pj][n_vec] (in the scratch buffer), or null.
 // Scratch: the caller's buffer (scratch, at least nonlocal_scratch_bytes(nl,
 // n_vec) bytes) or the context's growable buffer.  alpha_d as in nl_delta_kernel.
+// the packed complex contraction applies (FP64, at most 8 projectors per atom)
+template <class T>
+constexpr bool pack_rows() { return sizeof(T) == 8; }
+template <class T>
+static bool pack_rows(const NonlocalK& nl) { return pack_rows<T>() && nl.max_pj <= 8; }
+
 template <class T>
 static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
                                                    const typename C2<T>::type* proj, const double2* X,
@@ -484,6 +513,10 @@ static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
       hipLaunchKernelGGL((nl_contract_kernel<T, true>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
                          nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
                          nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X + c0, ldx, g, partial);
+    else if (pack_rows<T>(nl))
+      hipLaunchKernelGGL((nl_contract_kernel<T, false, pack_rows<T>()>), cgrid, dim3(256), 0, c->stream, proj,
+                         nl.sup_node.ptr, nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr,
+                         nl.chunk_order.ptr, nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X + c0, ldx, g, partial);
     else
       hipLaunchKernelGGL((nl_contract_kernel<T, false>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
                          nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
