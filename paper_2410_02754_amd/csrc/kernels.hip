@@ -101,11 +101,12 @@ constexpr int nl_col_blocks() { return sizeof(T) == 8 ? 1 : 2; }
 // used), k = four support entries per step, column = 16 of the tile's columns;
 // sixteen entries' operands are loaded before their MFMAs are issued.
 // REALP: the projector values are real (Gamma point), two real MFMAs per step.
-// PACK (FP64, complex values, n_pj <= 8): rows 0-7 carry the real parts and
-// rows 8-15 the imaginary parts of the projectors, so one MFMA against Re x
-// and one against Im x replace the four of the plain complex step; row chi and
-// row chi + 8 sit in the same lane (accumulator registers j and j + 2), where
-//   Re c = (p_r x_r)[chi] + (p_i x_i)[chi + 8],  Im c = (p_r x_i)[chi] - (p_i x_r)[chi + 8].
+// PACK (complex values, n_pj <= 8): rows 0-7 carry the real parts and rows
+// 8-15 the imaginary parts of the projectors, so one MFMA against Re x and one
+// against Im x replace the four of the plain complex step, and
+//   Re c = (p_r x_r)[chi] + (p_i x_i)[chi + 8],  Im c = (p_r x_i)[chi] - (p_i x_r)[chi + 8];
+// row chi + 8 is accumulator register j + 2 of the same lane (FP64) or register
+// j of the lane 32 above (FP32).
 template <class T, bool REALP, bool PACK = false>
 __global__ __launch_bounds__(256) void nl_contract_kernel(
     const typename C2<T>::type* __restrict__ proj, const int32_t* __restrict__ sup_node,
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
     const double2* __restrict__ X, int64_t ldx, int n_vec, typename C2<T>::type* __restrict__ partial) {
   typedef typename C2<T>::type CT;
   typedef typename Vec4<T>::type V4;
-  static_assert(!PACK || (!REALP && sizeof(T) == 8), "packed rows: FP64 complex projectors only");
+  static_assert(!PACK || !REALP, "packed rows: complex projector values only");
   constexpr int U = 4;                    // k-steps per batch
   constexpr int NCB = nl_col_blocks<T>();
   // each XCD takes a contiguous range of the (window, atom)-ordered chunks, so the
@@ -189,24 +190,46 @@ __global__ __launch_bounds__(256) void nl_contract_kernel(
     }
   }
   CT* out = partial + (size_t)ch * 2 * max_pj * n_vec;
+  if constexpr (PACK) {
 #pragma unroll
-  for (int j = 0; j < (PACK ? 2 : 4); ++j) {
-    const int x = acc_row<T>(lane, j);
-    if (x >= npj) continue;
+    for (int j = 0; j < 4; ++j) {
+      if (sizeof(T) == 8 && j >= 2) break;                       // FP64: rows 8-15
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      if (!cv[cb]) continue;
+      for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int sp = 0; sp < 2; ++sp) {
-        CT v;
-        if constexpr (PACK) {
-          v.x = cr[sp][cb][j] + ci[sp][cb][j + 2];
-          v.y = ci[sp][cb][j] - cr[sp][cb][j + 2];
-        } else {
+        for (int sp = 0; sp < 2; ++sp) {
+          // row x + 8: same lane (FP64) or the lane 32 above (FP32; every lane shuffles)
+          T hr, hi;
+          if constexpr (sizeof(T) == 8) {
+            hr = cr[sp][cb][j + 2];
+            hi = ci[sp][cb][j + 2];
+          } else {
+            hr = __shfl_down(cr[sp][cb][j], 32);
+            hi = __shfl_down(ci[sp][cb][j], 32);
+          }
+          const int x = acc_row<T>(lane, j);
+          if (x >= 8 || x >= npj || !cv[cb]) continue;             // FP32: lanes 32-63 hold rows 8-15
+          CT v;
+          v.x = cr[sp][cb][j] + hi;
+          v.y = ci[sp][cb][j] - hr;
+          out[(size_t)(2 * x + sp) * n_vec + col[cb]] = v;
+        }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = acc_row<T>(lane, j);
+      if (x >= npj) continue;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        if (!cv[cb]) continue;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+          CT v;
           v.x = cr[sp][cb][j];
           v.y = ci[sp][cb][j];
+          out[(size_t)(2 * x + sp) * n_vec + col[cb]] = v;
         }
-        out[(size_t)(2 * x + sp) * n_vec + col[cb]] = v;
       }
     }
   }
@@ -465,11 +488,8 @@ __global__ __launch_bounds__(256) void init_nl_kernel(
 // device array [n_atoms][2 max_pj][n_vec] (in the scratch buffer), or null.
 // Scratch: the caller's buffer (scratch, at least nonlocal_scratch_bytes(nl,
 // n_vec) bytes) or the context's growable buffer.  alpha_d as in nl_delta_kernel.
-// the packed complex contraction applies (FP64, at most 8 projectors per atom)
-template <class T>
-constexpr bool pack_rows() { return sizeof(T) == 8; }
-template <class T>
-static bool pack_rows(const NonlocalK& nl) { return pack_rows<T>() && nl.max_pj <= 8; }
+// the packed complex contraction applies (at most 8 projectors per atom)
+static bool pack_rows(const NonlocalK& nl) { return nl.max_pj <= 8; }
 
 template <class T>
 static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
@@ -513,8 +533,8 @@ static const typename C2<T>::type* nonlocal_coeffs(chfsi_ctx* c, NonlocalK& nl,
       hipLaunchKernelGGL((nl_contract_kernel<T, true>), cgrid, dim3(256), 0, c->stream, proj, nl.sup_node.ptr,
                          nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr, nl.chunk_order.ptr,
                          nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X + c0, ldx, g, partial);
-    else if (pack_rows<T>(nl))
-      hipLaunchKernelGGL((nl_contract_kernel<T, false, pack_rows<T>()>), cgrid, dim3(256), 0, c->stream, proj,
+    else if (pack_rows(nl))
+      hipLaunchKernelGGL((nl_contract_kernel<T, false, true>), cgrid, dim3(256), 0, c->stream, proj,
                          nl.sup_node.ptr, nl.chunk_atom.ptr, nl.chunk_begin.ptr, nl.chunk_end.ptr,
                          nl.chunk_order.ptr, nl.atom_npj.ptr, nl.max_pj, n_work, nct32, X + c0, ldx, g, partial);
     else
