@@ -51,6 +51,10 @@ SYSTEMS = {
     "gl_p2_nq4": lambda: synth.make_system(
         "gl_p2_nq4", n_cells=(3, 2, 2), box=(4.0, 3.0, 3.0), p=2, n_q=4, n_atoms=3, lmax=2,
         rcut_sigmas=4.0, kpts=[(0.0, 0.4, 0.0)], n_vec=8),
+    # complex projector values with 4 projectors per atom: the packed contraction rows
+    "k_l1": lambda: synth.make_system(
+        "k_l1", n_cells=(2, 3, 2), box=(4.0, 5.5, 4.5), p=3, kpts=[(0.17, 0.29, -0.11)],
+        n_atoms=3, lmax=1, rcut_sigmas=5.0, n_vec=16),
 }
 
 
@@ -99,7 +103,7 @@ def test_apply_H_block_of_wider_array_and_determinism():
     op.close()
 
 
-@pytest.mark.parametrize("name", ["tiny", "k_l2_aniso"])
+@pytest.mark.parametrize("name", ["tiny", "k_l2_aniso", "k_l1"])
 def test_apply_H_mixed(name):
     s = SYSTEMS[name]()
     H = _oracle(s)
