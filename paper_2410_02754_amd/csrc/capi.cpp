@@ -480,10 +480,18 @@ size_t chfsi_workspace_bytes(const chfsi_ctx* c, int ik, int n_vec, int op) {
     case CHFSI_OP_RAYLEIGH_RITZ:
       return std::max(std::max(nl_b, gram_b), resid_b) + rot_b;
     case CHFSI_OP_DENSITY: {
-      const int cols = c->nq == c->np1 ? 4 : 1;
-      const int64_t groups = std::min<int64_t>(std::max(1, cdiv(n_vec, cols)),
-                                               std::max(1, cdiv(4096, std::max(1, c->n_cells))));
-      return (size_t)groups * c->n_cells * c->nq3 * 4 * sizeof(double) + n * sizeof(double);
+      const int want = std::max(1, cdiv(4096, std::max(1, c->n_cells)));
+      int64_t groups;
+      size_t order = 0;
+      if (c->nq == c->np1) {
+        // sum-factorised kernel: 4-column chunks, at least two interleaved groups,
+        // and the tiled cell order it keeps
+        groups = std::max<int64_t>(1, std::min<int64_t>(cdiv(n_vec, 4), std::max(2, want)));
+        order = (size_t)c->n_cells * sizeof(int32_t);
+      } else {
+        groups = std::min<int64_t>(n_vec, want);
+      }
+      return (size_t)groups * c->n_cells * c->nq3 * 4 * sizeof(double) + n * sizeof(double) + order;
     }
     default:
       return 0;
